@@ -1,0 +1,545 @@
+"""FP64 CPU oracle for the block-sparse LNV / Hotelling hot path.
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
+baseline may import this package; the HIP product path never does.  It shares
+no code with the HIP library (`paper_2205_08941_amd`), and neither imports the
+other.  Only `synth` (seeded inputs, no solver arithmetic) feeds both.
+
+What it computes, and where it comes from:
+
+* block-sparse storage and truncated products -- the paper's statement that
+  the solver rests on sparse matrix storage and operations exploiting locality
+  (Background and Current Status); the operations are defined in `oracle.c`;
+* Hotelling's iteration Z <- 2Z - Z S Z for the overlap inverse -- the paper's
+  "linear scaling inversion of the overlap matrix" (Development Priorities),
+  by the textbook iteration of Hotelling (1943) / Schulz (1933);
+* LNV density-matrix minimisation, K = 3LSL - 2LSLSL -- the paper's linear
+  scaling O(N) ground-state solver (Background; Meeting the Exascale
+  Challenges), in the non-orthogonal form of Li, Nunes and Vanderbilt (1993)
+  and Nunes and Vanderbilt (1994), with conjugate gradients, an exact cubic
+  line search and a constant-electron-number projection.
+
+Parity pins (tests/test_oracle_*.py): dense masked matmul, np.trace, the dense
+inverse and the closed-form Hotelling residual, finite differences of the
+LNV energy, the generalised eigenvalue sum for untruncated cutoffs, the
+bond-projector closed form E = -4 N t, and the diamond shell counts.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "_liboracle.so")
+
+# status codes (same meaning as the library's documented codes)
+OK, EINVAL, ENOMEM, EPATTERN, EHIP, ENONFINITE, EDIVERGED, ENOTCONV, ERUNAWAY = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-shared",
+                               "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        L.orc_pattern_count.restype = ctypes.c_int64
+        L.orc_pattern_count.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P]
+        L.orc_pattern_fill.restype = None
+        L.orc_pattern_fill.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P]
+        L.orc_multiply.restype = None
+        L.orc_multiply.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, P, P, P, P, P, P,
+                                   ctypes.c_double, P, P, P, ctypes.c_int, ctypes.c_int]
+        L.orc_count_triples.restype = None
+        L.orc_count_triples.argtypes = [ctypes.c_int, P, P, P, P, P, P, P]
+        L.orc_trace_product.restype = ctypes.c_double
+        L.orc_trace_product.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+        _lib_handle = L
+    return _lib_handle
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Block-sparse storage
+# ---------------------------------------------------------------------------
+class Pattern:
+    """P_r: atom pairs with minimum-image distance below `cutoff`, diagonal included.
+
+    Block CSR: rowptr (int64, n+1), cols (int32, ascending per row).
+    """
+
+    def __init__(self, natoms, rowptr, cols, cutoff, positions, box):
+        self.natoms = int(natoms)
+        self.rowptr = np.ascontiguousarray(rowptr, np.int64)
+        self.cols = np.ascontiguousarray(cols, np.int32)
+        self.cutoff = float(cutoff)
+        self.positions = np.ascontiguousarray(positions, np.float64)
+        self.box = np.ascontiguousarray(box, np.float64)
+        self._tmap = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def rows(self) -> np.ndarray:
+        return np.repeat(np.arange(self.natoms, dtype=np.int32), np.diff(self.rowptr))
+
+    def keys(self) -> np.ndarray:
+        return self.rows().astype(np.int64) * self.natoms + self.cols
+
+    def find(self, rows, cols) -> np.ndarray:
+        """Slots of (rows, cols), -1 where absent."""
+        keys = self.keys()
+        q = np.asarray(rows, np.int64) * self.natoms + np.asarray(cols, np.int64)
+        s = np.searchsorted(keys, q)
+        s = np.minimum(s, len(keys) - 1)
+        return np.where(keys[s] == q, s, -1)
+
+    def transpose_map(self) -> np.ndarray:
+        """Slot of (j, i) for every slot (i, j); the pattern is symmetric by construction."""
+        if self._tmap is None:
+            t = self.find(self.cols, self.rows())
+            if np.any(t < 0):
+                raise ValueError("pattern is not symmetric")
+            self._tmap = t
+        return self._tmap
+
+    def diag_slots(self) -> np.ndarray:
+        return self.find(np.arange(self.natoms), np.arange(self.natoms))
+
+
+def create_pattern(positions, box, cutoff) -> Pattern:
+    """Brute force over all atom pairs, strict d^2 < r^2 under the minimum-image rule."""
+    pos = np.ascontiguousarray(positions, np.float64)
+    bx = np.ascontiguousarray(box, np.float64)
+    n = len(pos)
+    cnt = np.zeros(n, np.int64)
+    L = _lib()
+    L.orc_pattern_count(n, _p(pos), _p(bx), float(cutoff), _p(cnt))
+    rowptr = np.zeros(n + 1, np.int64)
+    np.cumsum(cnt, out=rowptr[1:])
+    cols = np.zeros(int(rowptr[-1]), np.int32)
+    L.orc_pattern_fill(n, _p(pos), _p(bx), float(cutoff), _p(rowptr), _p(cols))
+    return Pattern(n, rowptr, cols, cutoff, pos, bx)
+
+
+class Matrix:
+    """Block-sparse matrix: pattern + blocks (nnz, b, b) in CSR order."""
+
+    def __init__(self, pattern: Pattern, b: int, blocks: Optional[np.ndarray] = None):
+        self.pattern = pattern
+        self.b = int(b)
+        if blocks is None:
+            blocks = np.zeros((pattern.nnz, b, b))
+        self.blocks = np.ascontiguousarray(blocks, np.float64)
+        assert self.blocks.shape == (pattern.nnz, b, b)
+
+    def copy(self) -> "Matrix":
+        return Matrix(self.pattern, self.b, self.blocks.copy())
+
+    def zeros_like(self) -> "Matrix":
+        return Matrix(self.pattern, self.b)
+
+    def to_dense(self) -> np.ndarray:
+        n, b = self.pattern.natoms, self.b
+        D = np.zeros((n, b, n, b))
+        D[self.pattern.rows(), :, self.pattern.cols, :] = self.blocks
+        return D.reshape(n * b, n * b)
+
+    @property
+    def nrows(self) -> int:
+        return self.pattern.natoms * self.b
+
+
+def from_blocks(pattern: Pattern, b: int, rows, cols, blocks) -> Matrix:
+    """Place a list of blocks into a pattern; every block must fall inside it."""
+    s = pattern.find(rows, cols)
+    if np.any(s < 0):
+        raise ValueError("block outside the pattern")
+    M = Matrix(pattern, b)
+    np.add.at(M.blocks, s, blocks)
+    return M
+
+
+def from_dense(pattern: Pattern, b: int, D: np.ndarray) -> Matrix:
+    n = pattern.natoms
+    D4 = D.reshape(n, b, n, b)
+    return Matrix(pattern, b, D4[pattern.rows(), :, pattern.cols, :])
+
+
+def identity(pattern: Pattern, b: int, alpha: float = 1.0) -> Matrix:
+    M = Matrix(pattern, b)
+    M.blocks[pattern.diag_slots()] = alpha * np.eye(b)
+    return M
+
+
+def mask_copy(src: Matrix, pattern: Pattern) -> Matrix:
+    """mask_P(src): blocks of src kept where they fall in `pattern`, zero elsewhere."""
+    out = Matrix(pattern, src.b)
+    s = src.pattern.find(pattern.rows(), pattern.cols)
+    ok = s >= 0
+    out.blocks[ok] = src.blocks[s[ok]]
+    return out
+
+
+def multiply_truncate(alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix,
+                      row_begin: int = 0, row_end: Optional[int] = None) -> None:
+    """C <- alpha * mask_{P_C}(A B) + beta * C (in place), rows [row_begin, row_end)."""
+    n = C.pattern.natoms
+    if not (A.pattern.natoms == B.pattern.natoms == n and A.b == B.b == C.b):
+        raise ValueError("pattern mismatch")
+    if row_end is None:
+        row_end = n
+    _lib().orc_multiply(n, C.b, float(alpha),
+                        _p(A.pattern.rowptr), _p(A.pattern.cols), _p(A.blocks),
+                        _p(B.pattern.rowptr), _p(B.pattern.cols), _p(B.blocks),
+                        float(beta), _p(C.pattern.rowptr), _p(C.pattern.cols), _p(C.blocks),
+                        int(row_begin), int(row_end))
+
+
+def product(A: Matrix, B: Matrix, pattern: Pattern) -> Matrix:
+    C = Matrix(pattern, A.b)
+    multiply_truncate(1.0, A, B, 0.0, C)
+    return C
+
+
+def count_triples(PA: Pattern, PB: Pattern, PC: Pattern) -> np.ndarray:
+    """Block triples (i,k,j) of mask_C(A B), per row of C (int64)."""
+    out = np.zeros(PC.natoms, np.int64)
+    _lib().orc_count_triples(PC.natoms, _p(PA.rowptr), _p(PA.cols), _p(PB.rowptr),
+                             _p(PB.cols), _p(PC.rowptr), _p(PC.cols), _p(out))
+    return out
+
+
+def trace_product(A: Matrix, B: Matrix) -> float:
+    """Tr(A B), FP64."""
+    return float(_lib().orc_trace_product(A.pattern.natoms, A.b,
+                                          _p(A.pattern.rowptr), _p(A.pattern.cols), _p(A.blocks),
+                                          _p(B.pattern.rowptr), _p(B.pattern.cols), _p(B.blocks)))
+
+
+def trace(A: Matrix) -> float:
+    d = A.pattern.diag_slots()
+    return float(np.trace(A.blocks[d], axis1=1, axis2=2).sum())
+
+
+def dot(A: Matrix, B: Matrix) -> float:
+    """Frobenius inner product <A, B> of two matrices on the same pattern."""
+    assert A.pattern is B.pattern
+    return float(np.dot(A.blocks.ravel(), B.blocks.ravel()))
+
+
+def transpose(M: Matrix) -> Matrix:
+    t = M.pattern.transpose_map()
+    return Matrix(M.pattern, M.b, np.transpose(M.blocks[t], (0, 2, 1)))
+
+
+def symmetrize(M: Matrix) -> Matrix:
+    """(M + M^T) / 2, blockwise: (i,j) <- (M_ij + M_ji^T) / 2."""
+    T = transpose(M)
+    return Matrix(M.pattern, M.b, 0.5 * (M.blocks + T.blocks))
+
+
+def derived_pattern(P: Pattern, cutoff: float) -> Pattern:
+    return create_pattern(P.positions, P.box, cutoff)
+
+
+# ---------------------------------------------------------------------------
+# Hotelling / Schulz iteration for the overlap inverse
+# ---------------------------------------------------------------------------
+@dataclass
+class HotellingResult:
+    Z: Matrix
+    status: int
+    iterations: int
+    residuals: List[float]
+    alpha: float
+
+
+def gershgorin_bound(S: Matrix) -> float:
+    """max over scalar rows of sum_j |S_ij|: an upper bound of the spectrum of S."""
+    n, b = S.pattern.natoms, S.b
+    rowsum = np.zeros(n * b)
+    rr = S.pattern.rows()
+    np.add.at(rowsum, (rr[:, None] * b + np.arange(b)[None, :]).ravel(),
+              np.abs(S.blocks).sum(axis=2).ravel())
+    return float(rowsum.max())
+
+
+def _hotelling_residual(T: Matrix, nb: int) -> float:
+    """||I - Z S||_F from T = Z S: sqrt(N_b - 2 Tr T + ||T||_F^2)."""
+    r2 = nb - 2.0 * trace(T) + float(np.dot(T.blocks.ravel(), T.blocks.ravel()))
+    return math.sqrt(max(r2, 0.0)) if math.isfinite(r2) else float("nan")
+
+
+def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: float = 1e-12,
+                      Z0: Optional[Matrix] = None) -> HotellingResult:
+    """Truncated Hotelling iteration Z <- sym(mask_Z(2Z - (Z S) Z)).
+
+    Start Z0 = I / rho with rho the Gershgorin bound of S (so 0 < rho^-1 lambda <= 1).
+    T = Z S is kept on P(r_Z + r_S), which holds it exactly, so the residual
+    ||I - Z S||_F = sqrt(N_b - 2 Tr T + ||T||_F^2) is exact.
+    Stops: residual < tol sqrt(N_b) (tol > 0); max_iter updates; stagnation (the
+    next residual is not smaller: keep the current Z, accepted only when its
+    residual is at most 0.1 sqrt(N_b)); divergence (residual above the first).
+    """
+    nb = S.nrows
+    PT = derived_pattern(z_pattern, z_pattern.cutoff + S.pattern.cutoff)
+    alpha = 1.0 / gershgorin_bound(S)
+    Z = identity(z_pattern, S.b, alpha) if Z0 is None else mask_copy(Z0, z_pattern)
+    T = product(Z, S, PT)
+    r = _hotelling_residual(T, nb)
+    if not math.isfinite(r):
+        return HotellingResult(Z, ENONFINITE, 0, [r], alpha)
+    hist, r0, it, status = [r], r, 0, OK
+    while True:
+        if tol > 0 and r < tol * math.sqrt(nb):
+            status = OK
+            break
+        if it == max_iter:
+            status = ENOTCONV if tol > 0 else OK
+            break
+        M = product(T, Z, z_pattern)
+        Znew = symmetrize(Matrix(z_pattern, S.b, 2.0 * Z.blocks - M.blocks))
+        Tnew = product(Znew, S, PT)
+        rnew = _hotelling_residual(Tnew, nb)
+        if not math.isfinite(rnew):
+            status = ENONFINITE
+            break
+        if rnew > r0:
+            status = EDIVERGED
+            break
+        if rnew >= r:
+            status = OK if r <= 0.1 * math.sqrt(nb) else EDIVERGED
+            break
+        Z, T, r = Znew, Tnew, rnew
+        it += 1
+        hist.append(r)
+    return HotellingResult(Z, status, it, hist, alpha)
+
+
+# ---------------------------------------------------------------------------
+# LNV density-matrix minimisation
+# ---------------------------------------------------------------------------
+CANONICAL, GRAND = 0, 1
+
+
+def lnv_initial_scale(nb: int, n_electrons: float, t2: float, t3: float) -> float:
+    """c such that N(c Z) = 2 (3 c^2 t2 - 2 c^3 t3) = N_e, the root nearest c0.
+
+    c0 solves 3 c^2 - 2 c^3 = N_e / (2 N_b) (the value for Z = S^-1 exactly).
+    Both are found by Newton's method from the middle of the bracket [0, 1]
+    where 3c^2 - 2c^3 is monotone.
+    """
+    nu = n_electrons / (2.0 * nb)
+
+    def newton(f, df, x):
+        for _ in range(100):
+            step = f(x) / df(x)
+            x -= step
+            if abs(step) <= 1e-16 * max(1.0, abs(x)):
+                break
+        return x
+
+    c0 = newton(lambda c: 3 * c * c - 2 * c ** 3 - nu, lambda c: 6 * c - 6 * c * c, 0.5)
+    c = newton(lambda c: 2 * (3 * c * c * t2 - 2 * c ** 3 * t3) - n_electrons,
+               lambda c: 2 * (6 * c * t2 - 6 * c * c * t3), c0)
+    return c
+
+
+@dataclass
+class LNVResult:
+    E: float
+    Omega: float
+    N: float
+    mu: float
+    alpha: float
+    dE: float
+    converged: bool
+    status: int
+    beta: float = 0.0
+    c: tuple = ()
+
+
+@dataclass
+class LNVState:
+    S: Matrix
+    H: Matrix
+    Z: Matrix
+    L: Matrix
+    n_electrons: float
+    mode: int
+    mu: float
+    tol_E: float
+    PX: Pattern
+    PZG: Pattern
+    n: int = 0
+    E_prev: float = float("nan")
+    D_prev: Optional[Matrix] = None
+    g_prev: Optional[Matrix] = None
+    Mg_prev: Optional[Matrix] = None
+    history: list = field(default_factory=list)
+
+
+def lnv_init(S: Matrix, H: Matrix, Z: Matrix, l_pattern: Pattern, n_electrons: float,
+             mode: int = CANONICAL, mu: float = 0.0, tol_E: float = 1e-8,
+             L0: Optional[Matrix] = None) -> LNVState:
+    """Set up the minimisation.  Without L0 the start is L0 = c mask_L(Z), c from
+    the cubic N(c Z) = N_e (t_m = Tr[(Z S)^m], T = Z S exact on P(r_Z + r_S))."""
+    r_x = l_pattern.cutoff + max(S.pattern.cutoff, H.pattern.cutoff)
+    PX = derived_pattern(l_pattern, r_x)
+    PZG = derived_pattern(l_pattern, Z.pattern.cutoff + l_pattern.cutoff)
+    if L0 is None:
+        PT = derived_pattern(Z.pattern, Z.pattern.cutoff + S.pattern.cutoff)
+        T = product(Z, S, PT)
+        T2 = product(T, T, PT)
+        t2 = trace_product(T, T)
+        t3 = trace_product(T2, T)
+        c = lnv_initial_scale(S.nrows, n_electrons, t2, t3)
+        Zl = mask_copy(Z, l_pattern)
+        L = Matrix(l_pattern, S.b, c * Zl.blocks)
+    else:
+        L = mask_copy(L0, l_pattern)
+    return LNVState(S=S, H=H, Z=Z, L=L, n_electrons=n_electrons, mode=mode, mu=mu,
+                    tol_E=tol_E, PX=PX, PZG=PZG)
+
+
+def _precondition(st: LNVState, G: Matrix) -> Matrix:
+    """M(G) = sym(mask_L((Z G) Z)): the S^-1-contravariant form of a gradient."""
+    ZG = product(st.Z, G, st.PZG)
+    return symmetrize(product(ZG, st.Z, st.L.pattern))
+
+
+def lnv_energy_terms(st: LNVState):
+    """X = L S, Y = L H, W = mask(X X), U = mask(Y X) on P_X and E, N from traces."""
+    PX = st.PX
+    X = product(st.L, st.S, PX)
+    Y = product(st.L, st.H, PX)
+    W = product(X, X, PX)
+    U = product(Y, X, PX)
+    E = 2.0 * (3.0 * trace_product(X, Y) - 2.0 * trace_product(W, Y))
+    N = 2.0 * (3.0 * trace_product(X, X) - 2.0 * trace_product(W, X))
+    return X, Y, W, U, E, N
+
+
+def lnv_gradients(st: LNVState, X, W, U):
+    """G_E = 2[3(HX + (HX)^T) - 2(HW + (HW)^T + S U)], G_N = 12 (S X - S W), on P_L, symmetrised.
+
+    These are dE/dL and dN/dL for E = 2 Tr[(3LSL - 2LSLSL) H], N = 2 Tr[(3LSL - 2LSLSL) S].
+    """
+    PL = st.L.pattern
+    HX = product(st.H, X, PL)
+    HW = product(st.H, W, PL)
+    SU = product(st.S, U, PL)
+    SX = product(st.S, X, PL)
+    SW = product(st.S, W, PL)
+    HXt, HWt = transpose(HX), transpose(HW)
+    GE = 6.0 * (HX.blocks + HXt.blocks) - 4.0 * (HW.blocks + HWt.blocks) - 4.0 * SU.blocks
+    GN = 12.0 * (SX.blocks - SW.blocks)
+    return symmetrize(Matrix(PL, st.L.b, GE)), symmetrize(Matrix(PL, st.L.b, GN))
+
+
+def lnv_step(st: LNVState) -> LNVResult:
+    """One LNV conjugate-gradient iteration with an exact cubic line search."""
+    PL, b = st.L.pattern, st.L.b
+    X, Y, W, U, E, N = lnv_energy_terms(st)
+    if not (math.isfinite(E) and math.isfinite(N)):
+        return LNVResult(E, float("nan"), N, st.mu, 0.0, float("nan"), False, ENONFINITE)
+    GE, GN = lnv_gradients(st, X, W, U)
+    PE, PN = _precondition(st, GE), _precondition(st, GN)
+    gn_pn = dot(GN, PN)
+    # G_N vanishes exactly only at an idempotent L; then N is stationary and the
+    # projection and correction are skipped, keeping the previous mu
+    canonical = st.mode == CANONICAL and gn_pn > 0.0
+    mu = dot(GN, PE) / gn_pn if canonical else st.mu
+    g = Matrix(PL, b, GE.blocks - mu * GN.blocks)
+    Mg = Matrix(PL, b, PE.blocks - mu * PN.blocks)
+    R = Matrix(PL, b, -Mg.blocks)
+    beta = 0.0
+    if st.n > 0 and st.n % 50 != 0 and st.g_prev is not None:
+        den = dot(st.g_prev, st.Mg_prev)
+        beta = max(0.0, dot(g, Matrix(PL, b, Mg.blocks - st.Mg_prev.blocks)) / den)
+    D = Matrix(PL, b, R.blocks + beta * st.D_prev.blocks) if beta != 0.0 else R.copy()
+    if dot(g, D) >= 0.0:
+        beta = 0.0
+        D = R.copy()
+    if canonical:
+        D = Matrix(PL, b, D.blocks - (dot(GN, D) / gn_pn) * PN.blocks)
+
+    # exact line search along L + a D: X(a) = X + a X_D, Y(a) = Y + a Y_D
+    PX = st.PX
+    XD = product(D, st.S, PX)
+    YD = product(D, st.H, PX)
+    Q = product(XD, XD, PX)
+    X1 = Matrix(PX, b, X.blocks + XD.blocks)
+    W1 = product(X1, X1, PX)
+    M1 = Matrix(PX, b, W1.blocks - W.blocks - Q.blocks)   # X XD + XD X
+    tp = trace_product
+    f = [tp(X, Y), tp(XD, Y) + tp(X, YD), tp(XD, YD), 0.0]
+    h = [tp(X, X), 2.0 * tp(X, XD), tp(XD, XD), 0.0]
+    gg = [tp(W, Y), tp(M1, Y) + tp(W, YD), tp(Q, Y) + tp(M1, YD), tp(Q, YD)]
+    kk = [tp(W, X), tp(M1, X) + tp(W, XD), tp(Q, X) + tp(M1, XD), tp(Q, XD)]
+    e = [2.0 * (3.0 * f[m] - 2.0 * gg[m]) for m in range(4)]
+    nn = [2.0 * (3.0 * h[m] - 2.0 * kk[m]) for m in range(4)]
+    c = [e[m] - mu * nn[m] for m in range(4)]
+    disc = c[2] * c[2] - 3.0 * c[1] * c[3]
+    status = OK
+    if not (disc >= 0.0):
+        status = ERUNAWAY
+    else:
+        den = c[2] + math.sqrt(disc)
+        if not (den > 0.0):
+            status = ERUNAWAY
+    dE = E - st.E_prev if st.n > 0 else float("nan")
+    Omega = E - mu * N
+    if status != OK:
+        return LNVResult(E, Omega, N, mu, 0.0, dE, False, status, beta, tuple(c))
+    a = -c[1] / den
+    Lnew = st.L.blocks + a * D.blocks
+    if canonical:
+        N_a = nn[0] + a * (nn[1] + a * (nn[2] + a * nn[3]))
+        delta = (st.n_electrons - N_a) / gn_pn
+        Lnew = Lnew + delta * PN.blocks
+    st.L = symmetrize(Matrix(PL, b, Lnew))
+    converged = st.n > 0 and abs(dE) < st.tol_E
+    st.E_prev = E
+    st.mu = mu
+    st.D_prev, st.g_prev, st.Mg_prev = D, g, Mg
+    st.n += 1
+    res = LNVResult(E, Omega, N, mu, a, dE, converged, OK, beta, tuple(c))
+    st.history.append(res)
+    return res
+
+
+def density_matrix(st: LNVState, pattern: Pattern) -> Matrix:
+    """K = 3 LSL - 2 LSLSL on `pattern`; exact when the pattern range is at most r_S
+    (W = X X is held on P(r_L + r_S) and W L must reach r_L beyond it)."""
+    X = product(st.L, st.S, st.PX)
+    W = product(X, X, st.PX)
+    K = product(X, st.L, pattern)
+    K2 = product(W, st.L, pattern)
+    return Matrix(pattern, st.L.b, 3.0 * K.blocks - 2.0 * K2.blocks)
