@@ -1,0 +1,262 @@
+/*
+ * bsm.h -- C ABI of the MI355X (gfx950) block-sparse linear-scaling DFT hot path.
+ *
+ * The paper (Bowler, Miyazaki, Nakata, Truflandier, "The CONQUEST code: large
+ * scale and linear scaling DFT") describes a ground-state solver built on
+ * sparse matrix storage and operations that keep every step local (section
+ * "Background and Current Status"), whose linear-scaling form depends on
+ * inverting the overlap matrix in linear time (section "Development
+ * Priorities"), and which it plans to run entirely on GPUs (section "Meeting
+ * the Exascale Challenges").  This library is that GPU solver's data-parallel
+ * core: atom-block sparse matrices truncated to spatial-cutoff patterns, their
+ * products and traces, the Hotelling iteration for S^-1 and the LNV
+ * (Li-Nunes-Vanderbilt) density-matrix minimisation with K = 3LSL - 2LSLSL.
+ *
+ * Conventions (all entry points):
+ *   - Return BSM_OK (0) on success and a negative BSM_E* code on failure;
+ *     bsm_last_error() then gives a message (thread-local, valid until the next
+ *     failing call on the same thread).  No C++ exception crosses this ABI.
+ *   - "device" pointers are HIP device memory of the context's device; "host"
+ *     pointers are ordinary CPU memory.
+ *   - Work is queued on the context's stream.  Calls that return a host scalar
+ *     (traces, dots, drivers) synchronise that stream; the others are
+ *     asynchronous.
+ *   - A failed call leaves its outputs unspecified and every handle valid.
+ *   - A context and everything created from it must be used from one host
+ *     thread at a time.
+ *
+ * Storage:
+ *   - A pattern P_r over N atoms holds every ordered atom pair (i, j) whose
+ *     minimum-image distance in the orthorhombic periodic box is strictly below
+ *     r (compared as d^2 < r^2 in FP64, no fused multiply-add), plus (i, i).
+ *     It is block CSR: row i lists its columns j in ascending order.  Patterns
+ *     are symmetric by construction.
+ *   - A matrix on a pattern with b orbitals per atom stores one b x b block per
+ *     pattern entry, row-major inside the block, blocks in CSR order:
+ *     nnzb * b * b elements.  Blocks are Gamma-point folded (the block of (i, j)
+ *     sums every periodic image of the pair).
+ *   - Atom order is the caller's; the library never permutes atoms.  Spatially
+ *     sorted atoms (Morton order) give better cache reuse in the products.
+ */
+#ifndef BSM_H
+#define BSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BSM_OK = 0,
+    BSM_EINVAL = -1,      /* bad argument (sizes, null pointers, aliasing) */
+    BSM_ENOMEM = -2,      /* device allocation failed */
+    BSM_EPATTERN = -3,    /* patterns or orbital counts do not match */
+    BSM_EHIP = -4,        /* a HIP runtime call failed */
+    BSM_ENONFINITE = -5,  /* a trace, residual or energy is NaN or infinite */
+    BSM_EDIVERGED = -6,   /* Hotelling residual grew: S not positive definite */
+    BSM_ENOTCONV = -7,    /* iteration limit reached before the tolerance */
+    BSM_ERUNAWAY = -8     /* LNV line search found no minimum (outside the basin) */
+};
+
+enum { BSM_F64 = 0, BSM_F32 = 1, BSM_BF16 = 2 };
+
+typedef struct bsm_ctx_s *bsm_ctx;
+typedef struct bsm_pattern_s *bsm_pattern;
+
+/* Optional allocator for all memory the library allocates itself (patterns,
+ * plans, driver scratch).  Must return device memory of the context's device,
+ * 256-byte aligned, or NULL on failure.  NULL callbacks select hipMalloc/hipFree. */
+typedef void *(*bsm_alloc_fn)(size_t bytes, void *user);
+typedef void (*bsm_free_fn)(void *ptr, void *user);
+
+/* A matrix view.  `blocks` is caller-owned device memory of
+ * nnzb(pattern) * b * b elements of `dtype`; the library never frees it. */
+typedef struct {
+    bsm_pattern pattern;
+    int dtype;            /* BSM_F64 for every entry point of this header */
+    void *blocks;
+} bsm_matrix;
+
+typedef struct {
+    int natoms;
+    int b;                /* orbitals per atom */
+    int64_t nnzb;         /* number of blocks */
+    int max_row;          /* longest row, in blocks */
+    double cutoff;        /* Angstrom */
+    double box[3];        /* Angstrom */
+    const int32_t *rowptr;  /* device, natoms + 1 */
+    const int32_t *cols;    /* device, nnzb, ascending within a row */
+    const int32_t *tmap;    /* device, nnzb: slot of (j, i) for slot (i, j) */
+    const int32_t *diag;    /* device, natoms: slot of (i, i) */
+    const double *pos;      /* device, natoms * 3: the positions it was built from */
+} bsm_pattern_info;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device` queueing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The context owns plan caches and
+ * reduction scratch.  Errors: BSM_EINVAL (out NULL or bad device), BSM_EHIP. */
+int bsm_ctx_create(int device, void *hip_stream, bsm_alloc_fn alloc, bsm_free_fn free_fn,
+                   void *user, bsm_ctx *out);
+int bsm_ctx_destroy(bsm_ctx ctx);
+int bsm_ctx_set_stream(bsm_ctx ctx, void *hip_stream);
+const char *bsm_last_error(void);
+
+/* Per-class timing of block products: with profiling on, every product launch
+ * (from any entry point, drivers included) is bracketed by HIP events on the
+ * context's stream.  Classes are (P_A, P_B, P_C) triples. */
+typedef struct {
+    int natoms, b;
+    double cutoff_a, cutoff_b, cutoff_c;  /* Angstrom */
+    int64_t launches;
+    double flops;        /* algorithmic flops summed over the launches */
+    double ms;           /* summed event time, milliseconds */
+} bsm_product_stat;
+
+/* enable != 0 clears the statistics and starts recording; 0 stops. */
+int bsm_ctx_set_profiling(bsm_ctx ctx, int enable);
+/* Synchronises the stream, then writes up to `max` classes (most time first)
+ * and their total number to *count. */
+int bsm_ctx_product_stats(bsm_ctx ctx, bsm_product_stat *out, int max, int *count);
+
+/* ---- patterns (paper: sparse storage exploiting locality, Background) -- */
+
+/* Build P_cutoff over `natoms` atoms at device positions `pos` (natoms x 3 FP64,
+ * Angstrom) in the orthorhombic periodic box `box` (host, 3 FP64), with `b`
+ * orbitals per atom.  GPU cell-list search (cells no smaller than the cutoff;
+ * fewer than three cells along an axis falls back to scanning that whole axis).
+ * The positions are copied.  Errors: BSM_EINVAL (natoms <= 0, b not in 1..16,
+ * cutoff <= 0, box <= 0, a row longer than 8192 blocks), BSM_ENOMEM, BSM_EHIP. */
+int bsm_create_pattern(bsm_ctx ctx, int natoms, int b, const double *pos, const double box[3],
+                       double cutoff, bsm_pattern *out);
+int bsm_pattern_destroy(bsm_pattern p);
+int bsm_pattern_get_info(bsm_pattern p, bsm_pattern_info *out);
+/* Copy rowptr (natoms + 1) and cols (nnzb) to host buffers; synchronises. */
+int bsm_pattern_copy_to_host(bsm_pattern p, int32_t *rowptr_host, int32_t *cols_host);
+
+/* ---- matrices: input and pattern-local operations ----------------------- */
+
+/* M <- 0, then M[(rows[n], cols[n])] = blocks[n] for n < count.  rows, cols
+ * (int32) and blocks (count * b * b FP64) are device arrays; (row, col) pairs
+ * must be distinct.  Errors: BSM_EPATTERN if a block falls outside M's pattern
+ * (synchronises to check), BSM_EINVAL. */
+int bsm_matrix_fill_blocks(bsm_ctx ctx, const bsm_matrix *M, int64_t count, const int32_t *rows,
+                           const int32_t *cols, const double *blocks);
+/* Y <- alpha X + beta Y (same pattern; beta == 0 ignores Y's old contents). */
+int bsm_axpby(bsm_ctx ctx, double alpha, const bsm_matrix *X, double beta, const bsm_matrix *Y);
+/* M <- (M + M^T) / 2 blockwise, in place. */
+int bsm_symmetrize(bsm_ctx ctx, const bsm_matrix *M);
+/* dst <- mask_{P_dst}(src): blocks of src inside dst's pattern, zero elsewhere.
+ * Same natoms and b.  Errors: BSM_EPATTERN, BSM_EINVAL (src aliases dst). */
+int bsm_mask_copy(bsm_ctx ctx, const bsm_matrix *src, const bsm_matrix *dst);
+/* M <- alpha I on M's pattern. */
+int bsm_set_identity(bsm_ctx ctx, const bsm_matrix *M, double alpha);
+/* *out = <A, B> = sum of elementwise products (same pattern); FP64; synchronises. */
+int bsm_dot(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, double *out);
+
+/* ---- the hot path ------------------------------------------------------- */
+
+/* C <- alpha mask_{P_C}(A B) + beta C.
+ * Block (i, j) of C in P_C receives sum over k with (i,k) in P_A and (k,j) in
+ * P_B of A_ik B_kj; pairs outside P_C are never formed (the truncation of a
+ * product back to its cutoff pattern, the paper's local sparse operations,
+ * Background).  beta == 0 ignores C's old contents.  The product plan for
+ * (P_A, P_B, P_C) is built on first use and cached in the context.
+ * Asynchronous.  Errors: BSM_EPATTERN (natoms or b differ), BSM_EINVAL (C's
+ * blocks alias A's or B's, dtype not F64), BSM_ENOMEM, BSM_EHIP. */
+int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *B,
+                          double beta, const bsm_matrix *C);
+/* Algorithmic flops of mask_{P_C}(A B): 2 b^3 per block triple (i, k, j). */
+int bsm_product_flops(bsm_ctx ctx, bsm_pattern PA, bsm_pattern PB, bsm_pattern PC, double *flops);
+
+/* *out = Tr(A B) = sum over (i,k) in P_A of sum_pq A_ik[p][q] B_ki[q][p], in FP64,
+ * blocks missing from P_B counting as zero.  Deterministic (fixed reduction
+ * order).  Synchronises.  Errors: BSM_EPATTERN, BSM_ENONFINITE (result not
+ * finite; *out is still written). */
+int bsm_trace_product(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, double *out);
+
+/* ---- Hotelling iteration for S^-1 (paper: linear-scaling inversion of the
+ *      overlap matrix, Development Priorities) ---------------------------- */
+typedef struct {
+    int max_iter;        /* maximum number of updates */
+    double tol;          /* stop when ||I - Z S||_F < tol sqrt(N_b); <= 0: run max_iter */
+    int init_given;      /* 0: Z0 = I / rho (rho = largest absolute row sum of S);
+                            1: start from Z's current contents */
+} hot_params;
+
+typedef struct {
+    int status;          /* BSM_OK, BSM_EDIVERGED, BSM_ENOTCONV or BSM_ENONFINITE */
+    int iterations;      /* updates accepted */
+    double alpha;        /* 1 / rho of the start */
+    double *residuals;   /* host, caller-owned, capacity entries (may be NULL) */
+    int capacity;
+    int n_residuals;     /* residual of Z0 and of every accepted update */
+    double product_flops; /* algorithmic flops of the products launched */
+} hot_result;
+
+/* Truncated Hotelling / Schulz iteration Z <- sym(mask_Z(2Z - (Z S) Z)) on Z's
+ * pattern, with T = Z S held exactly on P(r_Z + r_S) and the residual
+ * ||I - Z S||_F summed elementwise over T - I (a deterministic reduction).  Stops at
+ * the tolerance, at max_iter, or on stagnation (the next residual is not
+ * smaller: the current Z is kept; accepted when its residual is at most
+ * 0.1 sqrt(N_b), else BSM_EDIVERGED); a residual above the first gives
+ * BSM_EDIVERGED.  S and Z must be built from the same positions.  Returns the
+ * same code as result->status, except BSM_ENOTCONV, which returns BSM_OK with
+ * Z valid. */
+int hotelling_inverse(bsm_ctx ctx, const bsm_matrix *S, const bsm_matrix *Z,
+                      const hot_params *params, hot_result *result);
+
+/* ---- LNV density-matrix minimisation (paper: the linear-scaling O(N)
+ *      solver, Background; its full GPU form, Meeting the Exascale Challenges) */
+enum { LNV_CANONICAL = 0, LNV_GRAND = 1 };
+
+typedef struct {
+    double n_electrons;  /* N_e (spin-paired: E = 2 Tr KH, N = 2 Tr KS) */
+    int mode;            /* LNV_CANONICAL: mu from the gradients, N held at N_e;
+                            LNV_GRAND: fixed mu, no projection */
+    double mu;           /* fixed chemical potential for LNV_GRAND */
+    double tol_E;        /* converged when |E_n - E_(n-1)| < tol_E (Ha) */
+    int init_from_z;     /* 1: L <- c mask_L(Z) with N(c Z) = N_e; 0: use L as given */
+} lnv_params;
+
+typedef struct {
+    double E, Omega, N, mu;   /* at the L this step started from */
+    double alpha;             /* line-search step taken */
+    double beta;              /* conjugate-gradient coefficient used */
+    double dE;                /* E - E_previous (NaN on the first step) */
+    double c[4];              /* Omega(alpha) = c0 + c1 a + c2 a^2 + c3 a^3 */
+    int converged;
+    int status;
+    double product_flops;     /* algorithmic flops of this step's products */
+} lnv_result;
+
+typedef struct lnv_state_s lnv_state;
+
+/* Create a minimisation over L's pattern P_L.  S and H share one pattern; Z is
+ * the (truncated) S^-1 from hotelling_inverse.  L is caller-owned and is
+ * updated in place by every step.  Scratch (eight matrices on P(r_L + r_S),
+ * one on P(r_Z + r_L), twelve on P_L) comes from the context allocator; the
+ * wider patterns are built once per context and reused.
+ * Errors: BSM_EPATTERN, BSM_EINVAL, BSM_ENOMEM, BSM_ENONFINITE. */
+int lnv_state_create(bsm_ctx ctx, const bsm_matrix *S, const bsm_matrix *H, const bsm_matrix *Z,
+                     const bsm_matrix *L, const lnv_params *params, lnv_state **out);
+/* One conjugate-gradient iteration with an exact cubic line search:
+ * X = LS, Y = LH, W = XX, U = YX on P(r_L + r_S); E = 2(3 Tr XY - 2 Tr WY),
+ * N = 2(3 Tr XX - 2 Tr WX); gradients G_E, G_N on P_L; preconditioning
+ * M(G) = mask_L(Z G Z); Polak-Ribiere direction; Omega(alpha) cubic from
+ * traces; L <- sym(L + alpha D + delta M(G_N)) with delta restoring N_e.
+ * Returns result->status. */
+int lnv_step(lnv_state *st, lnv_result *result);
+/* Start over with new parameters on the same matrices (after Z or L changed):
+ * clears the conjugate-gradient history and, with init_from_z, recomputes
+ * L0 = c mask_L(Z).  *init_flops (may be NULL) receives the algorithmic flops of
+ * the two products that takes.  Patterns and product plans are kept. */
+int lnv_state_reset(lnv_state *st, const lnv_params *params, double *init_flops);
+int lnv_state_destroy(lnv_state *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSM_H */

@@ -291,9 +291,15 @@ def gershgorin_bound(S: Matrix) -> float:
 
 
 def _hotelling_residual(T: Matrix, nb: int) -> float:
-    """||I - Z S||_F from T = Z S: sqrt(N_b - 2 Tr T + ||T||_F^2)."""
-    r2 = nb - 2.0 * trace(T) + float(np.dot(T.blocks.ravel(), T.blocks.ravel()))
-    return math.sqrt(max(r2, 0.0)) if math.isfinite(r2) else float("nan")
+    """||I - Z S||_F from T = Z S, summed elementwise over (T - I)^2.
+
+    (Equal to sqrt(N_b - 2 Tr T + ||T||_F^2), but that form cancels to about
+    1e-13 N_b absolute in r^2, which hides residuals below ~1e-6.)
+    """
+    R = T.blocks.copy()
+    R[T.pattern.diag_slots()] -= np.eye(T.b)
+    r2 = float(np.dot(R.ravel(), R.ravel()))
+    return math.sqrt(r2) if math.isfinite(r2) else float("nan")
 
 
 def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: float = 1e-12,
@@ -302,7 +308,7 @@ def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: f
 
     Start Z0 = I / rho with rho the Gershgorin bound of S (so 0 < rho^-1 lambda <= 1).
     T = Z S is kept on P(r_Z + r_S), which holds it exactly, so the residual
-    ||I - Z S||_F = sqrt(N_b - 2 Tr T + ||T||_F^2) is exact.
+    ||I - Z S||_F is exact (summed elementwise over T - I).
     Stops: residual < tol sqrt(N_b) (tol > 0); max_iter updates; stagnation (the
     next residual is not smaller: keep the current Z, accepted only when its
     residual is at most 0.1 sqrt(N_b)); divergence (residual above the first).

@@ -1,0 +1,386 @@
+"""ctypes binding of libbsm (include/bsm.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch supplies device memory (the
+caching allocator, also for the library's own scratch through the allocator
+callbacks) and the stream.  Importing this module fails loudly when
+libbsm.so has not been built.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import math
+import os
+import sys
+import weakref
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsm.so")
+
+OK, EINVAL, ENOMEM, EPATTERN, EHIP, ENONFINITE, EDIVERGED, ENOTCONV, ERUNAWAY = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+F64, F32, BF16 = 0, 1, 2
+CANONICAL, GRAND = 0, 1
+
+_NAMES = {0: "BSM_OK", -1: "BSM_EINVAL", -2: "BSM_ENOMEM", -3: "BSM_EPATTERN", -4: "BSM_EHIP",
+          -5: "BSM_ENONFINITE", -6: "BSM_EDIVERGED", -7: "BSM_ENOTCONV", -8: "BSM_ERUNAWAY"}
+
+
+class BSMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------- C types
+c_void_p, c_int, c_int64, c_double, c_size_t = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                                ctypes.c_double, ctypes.c_size_t)
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("pattern", c_void_p), ("dtype", c_int), ("blocks", c_void_p)]
+
+
+class _PatternInfo(ctypes.Structure):
+    _fields_ = [("natoms", c_int), ("b", c_int), ("nnzb", c_int64), ("max_row", c_int),
+                ("cutoff", c_double), ("box", c_double * 3), ("rowptr", c_void_p), ("cols", c_void_p),
+                ("tmap", c_void_p), ("diag", c_void_p), ("pos", c_void_p)]
+
+
+class _HotParams(ctypes.Structure):
+    _fields_ = [("max_iter", c_int), ("tol", c_double), ("init_given", c_int)]
+
+
+class _HotResult(ctypes.Structure):
+    _fields_ = [("status", c_int), ("iterations", c_int), ("alpha", c_double),
+                ("residuals", ctypes.POINTER(c_double)), ("capacity", c_int), ("n_residuals", c_int),
+                ("product_flops", c_double)]
+
+
+class _ProductStat(ctypes.Structure):
+    _fields_ = [("natoms", c_int), ("b", c_int), ("cutoff_a", c_double), ("cutoff_b", c_double),
+                ("cutoff_c", c_double), ("launches", c_int64), ("flops", c_double), ("ms", c_double)]
+
+
+class _LNVParams(ctypes.Structure):
+    _fields_ = [("n_electrons", c_double), ("mode", c_int), ("mu", c_double), ("tol_E", c_double),
+                ("init_from_z", c_int)]
+
+
+class _LNVResult(ctypes.Structure):
+    _fields_ = [("E", c_double), ("Omega", c_double), ("N", c_double), ("mu", c_double),
+                ("alpha", c_double), ("beta", c_double), ("dE", c_double), ("c", c_double * 4),
+                ("converged", c_int), ("status", c_int), ("product_flops", c_double)]
+
+
+EXPORTS = {
+    "bsm_ctx_create": (c_int, [c_int, c_void_p, ALLOC_FN, FREE_FN, c_void_p, ctypes.POINTER(c_void_p)]),
+    "bsm_ctx_destroy": (c_int, [c_void_p]),
+    "bsm_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
+    "bsm_last_error": (ctypes.c_char_p, []),
+    "bsm_ctx_set_profiling": (c_int, [c_void_p, c_int]),
+    "bsm_ctx_product_stats": (c_int, [c_void_p, ctypes.POINTER(_ProductStat), c_int, ctypes.POINTER(c_int)]),
+    "bsm_create_pattern": (c_int, [c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_double), c_double,
+                                   ctypes.POINTER(c_void_p)]),
+    "bsm_pattern_destroy": (c_int, [c_void_p]),
+    "bsm_pattern_get_info": (c_int, [c_void_p, ctypes.POINTER(_PatternInfo)]),
+    "bsm_pattern_copy_to_host": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "bsm_matrix_fill_blocks": (c_int, [c_void_p, ctypes.POINTER(_Matrix), c_int64, c_void_p, c_void_p,
+                                       c_void_p]),
+    "bsm_axpby": (c_int, [c_void_p, c_double, ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix)]),
+    "bsm_symmetrize": (c_int, [c_void_p, ctypes.POINTER(_Matrix)]),
+    "bsm_mask_copy": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix)]),
+    "bsm_set_identity": (c_int, [c_void_p, ctypes.POINTER(_Matrix), c_double]),
+    "bsm_dot": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix), ctypes.POINTER(c_double)]),
+    "bsm_multiply_truncate": (c_int, [c_void_p, c_double, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                                      c_double, ctypes.POINTER(_Matrix)]),
+    "bsm_product_flops": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double)]),
+    "bsm_trace_product": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                                  ctypes.POINTER(c_double)]),
+    "hotelling_inverse": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                                  ctypes.POINTER(_HotParams), ctypes.POINTER(_HotResult)]),
+    "lnv_state_create": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                                 ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix), ctypes.POINTER(_LNVParams),
+                                 ctypes.POINTER(c_void_p)]),
+    "lnv_step": (c_int, [c_void_p, ctypes.POINTER(_LNVResult)]),
+    "lnv_state_destroy": (c_int, [c_void_p]),
+    "lnv_state_reset": (c_int, [c_void_p, ctypes.POINTER(_LNVParams), ctypes.POINTER(c_double)]),
+}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python paper_2205_08941_amd/build.py` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(code: int) -> None:
+    if code != OK:
+        raise BSMError(code, _lib.bsm_last_error().decode(errors="replace"))
+
+
+# ---------------------------------------------------------------- objects
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+def _close_all():
+    for c in list(_LIVE_CONTEXTS):
+        c.close()
+
+
+atexit.register(_close_all)
+
+
+class Context:
+    """Library context on one GPU; all work goes to `stream` (default: torch's current).
+
+    Patterns and LNV states created on a context are released before it, and
+    everything is released at interpreter exit while Python is still alive.
+    """
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None,
+                 use_torch_allocator: bool = True):
+        self._children = weakref.WeakSet()
+        self.handle = None
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._keep = {}
+        self._alloc_cb = ALLOC_FN(self._alloc) if use_torch_allocator else ALLOC_FN()
+        self._free_cb = FREE_FN(self._free) if use_torch_allocator else FREE_FN()
+        h = c_void_p()
+        _check(_lib.bsm_ctx_create(device, c_void_p(self.stream.cuda_stream), self._alloc_cb,
+                                   self._free_cb, None, ctypes.byref(h)))
+        self.handle = h
+        _LIVE_CONTEXTS.add(self)
+
+    def set_profiling(self, enable: bool) -> None:
+        """Time every product launch with HIP events on this context's stream."""
+        _check(_lib.bsm_ctx_set_profiling(self.handle, int(bool(enable))))
+
+    def product_stats(self) -> list:
+        """Per (P_A, P_B, P_C) class: launches, algorithmic flops, event milliseconds."""
+        n = c_int()
+        _check(_lib.bsm_ctx_product_stats(self.handle, None, 0, ctypes.byref(n)))
+        arr = (_ProductStat * max(n.value, 1))()
+        _check(_lib.bsm_ctx_product_stats(self.handle, arr, n.value, ctypes.byref(n)))
+        return [dict(natoms=a.natoms, b=a.b, cutoffs=(a.cutoff_a, a.cutoff_b, a.cutoff_c),
+                     launches=a.launches, flops=a.flops, ms=a.ms) for a in arr[: n.value]]
+
+    def _alloc(self, nbytes, user):
+        try:
+            with torch.cuda.stream(self.stream):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        p = t.data_ptr()
+        self._keep[p] = t
+        return p
+
+    def _free(self, ptr, user):
+        self._keep.pop(ptr, None)
+
+    def close(self):
+        # solver states before the patterns they point into
+        for ch in sorted(self._children, key=lambda o: not isinstance(o, LNV)):
+            ch.close()
+        if self.handle:
+            _lib.bsm_ctx_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
+
+
+class Pattern:
+    """P_cutoff over the atoms at `positions` (built on the GPU)."""
+
+    def __init__(self, ctx: Context, positions, box, cutoff: float, b: int):
+        self.ctx = ctx
+        pos = torch.as_tensor(np.asarray(positions, np.float64) if not torch.is_tensor(positions) else positions,
+                              dtype=torch.float64).to(ctx.device).contiguous()
+        bx = (c_double * 3)(*[float(v) for v in box])
+        h = c_void_p()
+        _check(_lib.bsm_create_pattern(ctx.handle, pos.shape[0], int(b), c_void_p(pos.data_ptr()), bx,
+                                       float(cutoff), ctypes.byref(h)))
+        self.handle = h
+        ctx._children.add(self)
+        info = _PatternInfo()
+        _check(_lib.bsm_pattern_get_info(h, ctypes.byref(info)))
+        self.natoms, self.b, self.nnzb, self.max_row = info.natoms, info.b, info.nnzb, info.max_row
+        self.cutoff, self.box = info.cutoff, tuple(info.box)
+
+    def to_host(self):
+        rp = np.zeros(self.natoms + 1, np.int32)
+        cols = np.zeros(max(self.nnzb, 1), np.int32)
+        _check(_lib.bsm_pattern_copy_to_host(self.handle, rp.ctypes.data_as(c_void_p),
+                                             cols.ctypes.data_as(c_void_p)))
+        return rp, cols[: self.nnzb]
+
+    def close(self):
+        if getattr(self, "handle", None) and self.ctx.handle:
+            _lib.bsm_pattern_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
+
+
+class Matrix:
+    """Block-sparse FP64 matrix on a pattern: blocks is a device tensor (nnzb, b, b)."""
+
+    def __init__(self, pattern: Pattern, blocks: Optional[torch.Tensor] = None):
+        self.pattern = pattern
+        shape = (pattern.nnzb, pattern.b, pattern.b)
+        if blocks is None:
+            blocks = torch.zeros(shape, dtype=torch.float64, device=pattern.ctx.device)
+        assert blocks.dtype == torch.float64 and tuple(blocks.shape) == shape and blocks.is_contiguous()
+        self.blocks = blocks
+        self._c = _Matrix(pattern.handle, F64, c_void_p(blocks.data_ptr()))
+
+    @property
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def fill_blocks(M: Matrix, rows, cols, blocks) -> None:
+    """M <- 0, then place the given blocks (must fall inside M's pattern)."""
+    dev = M.pattern.ctx.device
+    r = torch.as_tensor(np.asarray(rows, np.int32)).to(dev)
+    c = torch.as_tensor(np.asarray(cols, np.int32)).to(dev)
+    b = torch.as_tensor(np.ascontiguousarray(blocks, np.float64)).to(dev)
+    _check(_lib.bsm_matrix_fill_blocks(M.pattern.ctx.handle, M.c, len(r), c_void_p(r.data_ptr()),
+                                       c_void_p(c.data_ptr()), c_void_p(b.data_ptr())))
+
+
+def multiply_truncate(alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix) -> None:
+    _check(_lib.bsm_multiply_truncate(C.pattern.ctx.handle, float(alpha), A.c, B.c, float(beta), C.c))
+
+
+def product_flops(PA: Pattern, PB: Pattern, PC: Pattern) -> float:
+    f = c_double()
+    _check(_lib.bsm_product_flops(PC.ctx.handle, PA.handle, PB.handle, PC.handle, ctypes.byref(f)))
+    return f.value
+
+
+def trace_product(A: Matrix, B: Matrix) -> float:
+    out = c_double()
+    _check(_lib.bsm_trace_product(A.pattern.ctx.handle, A.c, B.c, ctypes.byref(out)))
+    return out.value
+
+
+def dot(A: Matrix, B: Matrix) -> float:
+    out = c_double()
+    _check(_lib.bsm_dot(A.pattern.ctx.handle, A.c, B.c, ctypes.byref(out)))
+    return out.value
+
+
+def axpby(alpha: float, X: Matrix, beta: float, Y: Matrix) -> None:
+    _check(_lib.bsm_axpby(Y.pattern.ctx.handle, float(alpha), X.c, float(beta), Y.c))
+
+
+def symmetrize(M: Matrix) -> None:
+    _check(_lib.bsm_symmetrize(M.pattern.ctx.handle, M.c))
+
+
+def mask_copy(src: Matrix, dst: Matrix) -> None:
+    _check(_lib.bsm_mask_copy(dst.pattern.ctx.handle, src.c, dst.c))
+
+
+def set_identity(M: Matrix, alpha: float = 1.0) -> None:
+    _check(_lib.bsm_set_identity(M.pattern.ctx.handle, M.c, float(alpha)))
+
+
+@dataclass
+class HotellingResult:
+    status: int
+    iterations: int
+    alpha: float
+    residuals: List[float]
+    product_flops: float = 0.0
+
+
+def hotelling_inverse(S: Matrix, Z: Matrix, max_iter: int = 100, tol: float = 1e-12,
+                      init_given: bool = False, raise_on_error: bool = True) -> HotellingResult:
+    cap = max_iter + 2
+    buf = (c_double * cap)()
+    prm = _HotParams(int(max_iter), float(tol), int(bool(init_given)))
+    res = _HotResult(0, 0, 0.0, ctypes.cast(buf, ctypes.POINTER(c_double)), cap, 0, 0.0)
+    code = _lib.hotelling_inverse(Z.pattern.ctx.handle, S.c, Z.c, ctypes.byref(prm), ctypes.byref(res))
+    if code != OK and raise_on_error:
+        _check(code)
+    return HotellingResult(res.status, res.iterations, res.alpha, list(buf[: min(res.n_residuals, cap)]),
+                           res.product_flops)
+
+
+@dataclass
+class LNVResult:
+    E: float
+    Omega: float
+    N: float
+    mu: float
+    alpha: float
+    beta: float
+    dE: float
+    c: tuple
+    converged: bool
+    status: int
+    product_flops: float
+
+
+class LNV:
+    """LNV minimisation state over L's pattern; L (a Matrix) is updated in place."""
+
+    def __init__(self, S: Matrix, H: Matrix, Z: Matrix, L: Matrix, n_electrons: float, mode: int = CANONICAL,
+                 mu: float = 0.0, tol_E: float = 1e-8, init_from_z: bool = True):
+        self.ctx = L.pattern.ctx
+        self.S, self.H, self.Z, self.L = S, H, Z, L   # keep the device buffers alive
+        self.n_electrons, self.mode, self.mu, self.tol_E = float(n_electrons), int(mode), float(mu), float(tol_E)
+        prm = _LNVParams(float(n_electrons), int(mode), float(mu), float(tol_E), int(bool(init_from_z)))
+        h = c_void_p()
+        _check(_lib.lnv_state_create(self.ctx.handle, S.c, H.c, Z.c, L.c, ctypes.byref(prm), ctypes.byref(h)))
+        self.handle = h
+        self.ctx._children.add(self)
+
+    def reset(self, init_from_z: bool = True) -> float:
+        """Restart from c mask_L(Z) (or the current L); returns the init products' flops."""
+        prm = _LNVParams(self.n_electrons, self.mode, self.mu, self.tol_E, int(bool(init_from_z)))
+        f = c_double()
+        _check(_lib.lnv_state_reset(self.handle, ctypes.byref(prm), ctypes.byref(f)))
+        return f.value
+
+    def step(self, raise_on_error: bool = False) -> LNVResult:
+        r = _LNVResult()
+        code = _lib.lnv_step(self.handle, ctypes.byref(r))
+        if code != OK and raise_on_error:
+            _check(code)
+        return LNVResult(r.E, r.Omega, r.N, r.mu, r.alpha, r.beta, r.dE, tuple(r.c), bool(r.converged),
+                         r.status, r.product_flops)
+
+    def close(self):
+        if getattr(self, "handle", None) and self.ctx.handle:
+            _lib.lnv_state_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()

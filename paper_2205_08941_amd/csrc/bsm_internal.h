@@ -1,0 +1,174 @@
+// Internal declarations shared by the host drivers and the HIP kernels of libbsm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/bsm.h"
+
+namespace bsm {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define BSM_HIP_TRY(expr)                                                              \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess)                                                          \
+            throw ::bsm::Error{BSM_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+#define BSM_REQUIRE(cond, code, msg)                                                   \
+    do {                                                                               \
+        if (!(cond)) throw ::bsm::Error{(code), (msg)};                                \
+    } while (0)
+
+// ---------------------------------------------------------------- memory
+class Context;
+
+// Device buffer from the context allocator; frees on destruction.
+struct DevBuf {
+    Context *ctx = nullptr;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(Context *c, size_t n);
+    ~DevBuf();
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept;
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Product plan: one work tile per (row i of C, run of up to `jt` consecutive
+// blocks of that row).  Cached per (P_A, P_B, P_C).
+struct Plan {
+    uint64_t ids[3] = {0, 0, 0};
+    double cutoffs[3] = {0, 0, 0};
+    int natoms = 0, b = 0;
+    int jt = 0;                 // output blocks per wavefront tile
+    int64_t ntiles = 0;
+    DevBuf tiles;               // int2 {row, first slot}
+    double flops = 0.0;         // algorithmic: 2 b^3 per block triple
+    int64_t triples = 0;
+};
+
+class Context {
+  public:
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bsm_alloc_fn alloc_fn = nullptr;
+    bsm_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    uint64_t next_pattern_id = 1;
+    // derived patterns (same atoms, another cutoff), owned here, keyed by (source id, cutoff)
+    std::map<std::pair<uint64_t, double>, bsm_pattern_s *> derived;
+    std::map<std::tuple<uint64_t, uint64_t, uint64_t>, std::unique_ptr<Plan>> plans;
+    // reduction scratch
+    DevBuf red_partials;        // double[kRedBlocks * kRedSlots]
+    DevBuf err_flag;            // int
+    double *host_scalars = nullptr;  // pinned host, kRedSlots doubles
+    // product timing (bsm_ctx_set_profiling)
+    struct ProfRec {
+        const Plan *plan;
+        hipEvent_t start, stop;
+    };
+    bool profiling = false;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> event_pool;
+    struct ProfAcc {
+        int64_t launches = 0;
+        double flops = 0.0, ms = 0.0;
+    };
+    // launches of plans whose patterns were destroyed while profiling
+    std::map<std::tuple<int, int, double, double, double>, ProfAcc> retired;
+    hipEvent_t take_event();
+    void clear_profile();
+
+    void *allocate(size_t bytes);
+    void release(void *p);
+    void forget_pattern(uint64_t id);
+};
+
+static constexpr int kRedBlocks = 1024;   // fixed grid for deterministic reductions
+static constexpr int kRedSlots = 16;      // traces computed by one fused launch, at most
+
+}  // namespace bsm
+
+struct bsm_ctx_s {
+    bsm::Context c;
+};
+
+struct bsm_pattern_s {
+    bsm::Context *ctx = nullptr;
+    uint64_t id = 0;
+    int natoms = 0, b = 0, max_row = 0;
+    int64_t nnzb = 0;
+    double cutoff = 0.0;
+    double box[3] = {0, 0, 0};
+    bsm::DevBuf pos, rowptr, cols, tmap, diag, rowidx;   // rowidx: row of every slot
+};
+
+namespace bsm {
+
+// ---------------------------------------------------------------- helpers
+int64_t nelems(const bsm_pattern_s *p);
+void check_matrix(const bsm_matrix *M, const char *name);
+void check_same_shape(const bsm_matrix *A, const bsm_matrix *B);
+bsm_pattern_s *make_pattern(Context *ctx, int natoms, int b, const double *pos_dev,
+                            const double box[3], double cutoff);
+// A pattern over the same atoms with another cutoff (owned by the caller).
+bsm_pattern_s *derived_pattern(const bsm_pattern_s *p, double cutoff);
+// The same, cached in (and owned by) the context until the source pattern or the
+// context is destroyed, so repeated driver calls reuse patterns and plans.
+const bsm_pattern_s *derived_pattern_cached(const bsm_pattern_s *p, double cutoff);
+void destroy_pattern(bsm_pattern_s *p);
+Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C);
+
+// ---------------------------------------------------------------- launches
+void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
+                        const double *A, const bsm_pattern_s *PB, const double *B, double beta,
+                        const bsm_pattern_s *PC, double *C);
+int64_t count_triples(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB,
+                      const bsm_pattern_s *PC, const Plan *plan);
+void build_tiles(Context *ctx, const bsm_pattern_s *PC, Plan *plan);
+
+// Traces of products Tr(A_n B_n) for up to kRedSlots pairs in one pass; A_n all
+// on one pattern, B_n all on one pattern.  Results to host `out`.  Synchronises.
+void trace_products(Context *ctx, int count, const bsm_pattern_s *PA, const double *const *A,
+                    const bsm_pattern_s *PB, const double *const *B, double *out);
+// <A_n, B_n> (same pattern) for up to kRedSlots pairs.  Synchronises.
+void dots(Context *ctx, int count, const bsm_pattern_s *P, const double *const *A,
+          const double *const *B, double *out);
+double trace_single(Context *ctx, const bsm_pattern_s *P, const double *A);
+double max_abs_row_sum(Context *ctx, const bsm_pattern_s *P, const double *A);
+// ||A - I||_F^2, elementwise.  Synchronises.
+double dist_identity_sq(Context *ctx, const bsm_pattern_s *P, const double *A);
+
+void axpby(Context *ctx, int64_t n, double alpha, const double *x, double beta, double *y);
+// z <- a x + b y + c z (z may be x or y elementwise-aliased: per-element update)
+void axpbypcz(Context *ctx, int64_t n, double a, const double *x, double b, const double *y,
+              double c, double *z);
+void symmetrize(Context *ctx, const bsm_pattern_s *P, double *M);
+// out <- alpha (M + M^T) + beta out; out must not alias M
+void add_transpose(Context *ctx, const bsm_pattern_s *P, double alpha, const double *M, double beta,
+                   double *out);
+void mask_copy(Context *ctx, const bsm_pattern_s *Psrc, const double *src, const bsm_pattern_s *Pdst,
+               double *dst);
+void set_identity(Context *ctx, const bsm_pattern_s *P, double alpha, double *M);
+void fill_blocks(Context *ctx, const bsm_pattern_s *P, double *M, int64_t count, const int32_t *rows,
+                 const int32_t *cols, const double *blocks);
+
+}  // namespace bsm

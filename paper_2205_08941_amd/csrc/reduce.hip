@@ -1,0 +1,285 @@
+// Deterministic FP64 reductions: traces of products, Frobenius inner products,
+// traces and the largest absolute row sum.
+//
+// The energy, electron count and their line-search polynomials of the LNV
+// solver, and the Hotelling residual, are all traces of products of sparse
+// matrices; they are read back to the host as a handful of FP64 scalars.
+//
+// Every reduction runs on a grid fixed by the input size, each workgroup sums
+// a fixed range in a fixed tree order, and a second one-workgroup pass adds the
+// partial sums in workgroup order: the result is bitwise reproducible.
+#include "bsm_internal.h"
+
+#include <cmath>
+
+namespace bsm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kChunk = 256;   // slots per chunk: one transpose lookup per thread
+
+struct Ptrs {
+    const double *p[kRedSlots];
+};
+
+template <int CNT>
+__device__ inline void block_reduce_store(double (&acc)[CNT], int count, double *__restrict__ partials)
+{
+    __shared__ double red[kThreads / 64][kRedSlots];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int n = 0; n < count; ++n) {
+        double v = acc[n];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[w][n] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < count) {
+        double v = 0.0;
+        for (int q = 0; q < kThreads / 64; ++q) v += red[q][threadIdx.x];
+        partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+__device__ inline int find_in_row(const int *__restrict__ rowptr, const int *__restrict__ cols, int i, int j)
+{
+    int lo = rowptr[i], hi = rowptr[i + 1], end = hi;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (cols[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < end && cols[lo] == j) ? lo : -1;
+}
+
+// Tr(A_n B_n) = sum over slots s = (i,k) of A of sum_pq A_n[s][p][q] B_n[t][q][p],
+// t = slot of (k, i) in B's pattern (-1: block absent, contributes zero).
+template <int CNT>
+__global__ __launch_bounds__(kThreads) void k_trace_products(
+    int count, int b, int64_t nnzA, const int *__restrict__ colsA, const int *__restrict__ rowsA,
+    const int *__restrict__ tmapA, int same_pattern, const int *__restrict__ rpB,
+    const int *__restrict__ colsB, Ptrs A, Ptrs Bp, double *__restrict__ partials)
+{
+    __shared__ int tslot[kChunk];
+    double acc[CNT];
+#pragma unroll
+    for (int n = 0; n < CNT; ++n) acc[n] = 0.0;
+    const int bb = b * b;
+    const int64_t nchunks = (nnzA + kChunk - 1) / kChunk;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t base = ch * kChunk;
+        const int nsl = (int)min((int64_t)kChunk, nnzA - base);
+        __syncthreads();
+        if (threadIdx.x < nsl) {
+            const int64_t s = base + threadIdx.x;
+            tslot[threadIdx.x] = same_pattern ? tmapA[s] : find_in_row(rpB, colsB, colsA[s], rowsA[s]);
+        }
+        __syncthreads();
+        const int nel = nsl * bb;
+        for (int e = threadIdx.x; e < nel; e += kThreads) {
+            const int ls = e / bb, r = e - ls * bb;
+            const int p = r / b, q = r - p * b;
+            const int t = tslot[ls];
+            if (t < 0) continue;
+            const int64_t ia = (base + ls) * bb + r;
+            const int64_t ib = (int64_t)t * bb + q * b + p;
+#pragma unroll
+            for (int n = 0; n < CNT; ++n)
+                if (n < count) acc[n] = fma(A.p[n][ia], Bp.p[n][ib], acc[n]);
+        }
+    }
+    block_reduce_store<CNT>(acc, count, partials);
+}
+
+template <int CNT>
+__global__ __launch_bounds__(kThreads) void k_dots(int count, int64_t nel, Ptrs A, Ptrs Bp,
+                                                    double *__restrict__ partials)
+{
+    double acc[CNT];
+#pragma unroll
+    for (int n = 0; n < CNT; ++n) acc[n] = 0.0;
+    const int64_t per = (nel + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = per * blockIdx.x, hi = min(nel, lo + per);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += kThreads) {
+#pragma unroll
+        for (int n = 0; n < CNT; ++n)
+            if (n < count) acc[n] = fma(A.p[n][e], Bp.p[n][e], acc[n]);
+    }
+    block_reduce_store<CNT>(acc, count, partials);
+}
+
+__global__ __launch_bounds__(kThreads) void k_trace_single(int n, int b, const int *__restrict__ diag,
+                                                           const double *__restrict__ A,
+                                                           double *__restrict__ partials)
+{
+    double acc[1] = {0.0};
+    const int per = (n + gridDim.x - 1) / gridDim.x;
+    const int lo = per * blockIdx.x, hi = min(n, lo + per);
+    for (int i = lo + threadIdx.x; i < hi; i += kThreads) {
+        const double *d = A + (int64_t)diag[i] * b * b;
+        double s = 0.0;
+        for (int p = 0; p < b; ++p) s += d[p * b + p];
+        acc[0] += s;
+    }
+    block_reduce_store<1>(acc, 1, partials);
+}
+
+// ||M - I||_F^2 summed elementwise (the identity sits on the diagonal slots).
+__global__ __launch_bounds__(kThreads) void k_dist_identity(int64_t nnz, int b, const int *__restrict__ rows,
+                                                            const int *__restrict__ cols,
+                                                            const double *__restrict__ M,
+                                                            double *__restrict__ partials)
+{
+    double acc[1] = {0.0};
+    const int bb = b * b;
+    const int64_t nel = nnz * bb;
+    const int64_t per = (nel + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = per * blockIdx.x, hi = min(nel, lo + per);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += kThreads) {
+        const int64_t s = e / bb;
+        const int r = (int)(e - s * bb);
+        const bool one = rows[s] == cols[s] && (r / b) == (r % b);
+        const double v = M[e] - (one ? 1.0 : 0.0);
+        acc[0] = fma(v, v, acc[0]);
+    }
+    block_reduce_store<1>(acc, 1, partials);
+}
+
+// Partial sums of every slot n added in workgroup order (one workgroup).
+__global__ __launch_bounds__(kThreads) void k_finish(int count, int nparts, const double *__restrict__ partials,
+                                                     double *__restrict__ out)
+{
+    __shared__ double red[kThreads];
+    for (int n = 0; n < count; ++n) {
+        double v = 0.0;
+        const int per = (nparts + kThreads - 1) / kThreads;
+        const int lo = threadIdx.x * per, hi = min(nparts, lo + per);
+        for (int q = lo; q < hi; ++q) v += partials[(size_t)n * nparts + q];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = kThreads / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[n] = red[0];
+        __syncthreads();
+    }
+}
+
+// Largest absolute row sum (max over scalar rows of sum_j |A_ij|); max is
+// order-independent, so an integer atomicMax on the non-negative bit pattern is exact.
+__global__ void k_row_abs_max(int n, int b, const int *__restrict__ rowptr, const double *__restrict__ A,
+                              unsigned long long *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * b) return;
+    const int i = (int)(t / b), p = (int)(t - (int64_t)i * b);
+    double s = 0.0;
+    for (int sl = rowptr[i]; sl < rowptr[i + 1]; ++sl) {
+        const double *blk = A + (int64_t)sl * b * b + p * b;
+        for (int q = 0; q < b; ++q) s += fabs(blk[q]);
+    }
+    if (!(s >= 0.0)) s = __builtin_inf();   // NaN row: report as non-finite
+    atomicMax(out, (unsigned long long)__double_as_longlong(s));
+}
+
+int grid_for(int64_t work)
+{
+    int64_t g = (work + kThreads - 1) / kThreads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, kRedBlocks));
+}
+
+void finish(Context *ctx, int count, int nparts, double *out)
+{
+    hipStream_t st = ctx->stream;
+    double *dev_out = ctx->red_partials.as<double>() + (size_t)kRedSlots * kRedBlocks;
+    k_finish<<<1, kThreads, 0, st>>>(count, nparts, ctx->red_partials.as<double>(), dev_out);
+    BSM_HIP_TRY(hipGetLastError());
+    BSM_HIP_TRY(hipMemcpyAsync(ctx->host_scalars, dev_out, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+    BSM_HIP_TRY(hipStreamSynchronize(st));
+    for (int n = 0; n < count; ++n) out[n] = ctx->host_scalars[n];
+}
+
+}  // namespace
+
+void trace_products(Context *ctx, int count, const bsm_pattern_s *PA, const double *const *A,
+                    const bsm_pattern_s *PB, const double *const *B, double *out)
+{
+    BSM_REQUIRE(count >= 1 && count <= kRedSlots, BSM_EINVAL, "bad trace count");
+    Ptrs pa{}, pb{};
+    for (int n = 0; n < count; ++n) {
+        pa.p[n] = A[n];
+        pb.p[n] = B[n];
+    }
+    const int64_t nchunks = (PA->nnzb + kChunk - 1) / kChunk;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, kRedBlocks));
+    const int same = (PA == PB) ? 1 : 0;
+    hipStream_t st = ctx->stream;
+#define LAUNCH(C)                                                                                    \
+    k_trace_products<C><<<grid, kThreads, 0, st>>>(count, PA->b, PA->nnzb, PA->cols.as<int>(),        \
+                                                   PA->rowidx.as<int>(), PA->tmap.as<int>(), same,   \
+                                                   PB->rowptr.as<int>(), PB->cols.as<int>(), pa, pb, \
+                                                   ctx->red_partials.as<double>())
+    if (count == 1) LAUNCH(1);
+    else if (count <= 4) LAUNCH(4);
+    else LAUNCH(kRedSlots);
+#undef LAUNCH
+    BSM_HIP_TRY(hipGetLastError());
+    finish(ctx, count, grid, out);
+}
+
+void dots(Context *ctx, int count, const bsm_pattern_s *P, const double *const *A, const double *const *B,
+          double *out)
+{
+    BSM_REQUIRE(count >= 1 && count <= kRedSlots, BSM_EINVAL, "bad dot count");
+    Ptrs pa{}, pb{};
+    for (int n = 0; n < count; ++n) {
+        pa.p[n] = A[n];
+        pb.p[n] = B[n];
+    }
+    const int64_t nel = nelems(P);
+    const int grid = grid_for(nel);
+    hipStream_t st = ctx->stream;
+    if (count == 1) k_dots<1><<<grid, kThreads, 0, st>>>(count, nel, pa, pb, ctx->red_partials.as<double>());
+    else if (count <= 4) k_dots<4><<<grid, kThreads, 0, st>>>(count, nel, pa, pb, ctx->red_partials.as<double>());
+    else k_dots<kRedSlots><<<grid, kThreads, 0, st>>>(count, nel, pa, pb, ctx->red_partials.as<double>());
+    BSM_HIP_TRY(hipGetLastError());
+    finish(ctx, count, grid, out);
+}
+
+double trace_single(Context *ctx, const bsm_pattern_s *P, const double *A)
+{
+    const int grid = grid_for(P->natoms);
+    k_trace_single<<<grid, kThreads, 0, ctx->stream>>>(P->natoms, P->b, P->diag.as<int>(), A,
+                                                       ctx->red_partials.as<double>());
+    BSM_HIP_TRY(hipGetLastError());
+    double out = 0.0;
+    finish(ctx, 1, grid, &out);
+    return out;
+}
+
+double dist_identity_sq(Context *ctx, const bsm_pattern_s *P, const double *A)
+{
+    const int grid = grid_for(nelems(P));
+    k_dist_identity<<<grid, kThreads, 0, ctx->stream>>>(P->nnzb, P->b, P->rowidx.as<int>(), P->cols.as<int>(), A,
+                                                        ctx->red_partials.as<double>());
+    BSM_HIP_TRY(hipGetLastError());
+    double out = 0.0;
+    finish(ctx, 1, grid, &out);
+    return out;
+}
+
+double max_abs_row_sum(Context *ctx, const bsm_pattern_s *P, const double *A)
+{
+    hipStream_t st = ctx->stream;
+    unsigned long long *dv = reinterpret_cast<unsigned long long *>(ctx->red_partials.as<double>() +
+                                                                    (size_t)kRedSlots * kRedBlocks + kRedSlots);
+    BSM_HIP_TRY(hipMemsetAsync(dv, 0, sizeof(unsigned long long), st));
+    const int64_t rows = (int64_t)P->natoms * P->b;
+    k_row_abs_max<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(P->natoms, P->b, P->rowptr.as<int>(), A, dv);
+    BSM_HIP_TRY(hipGetLastError());
+    BSM_HIP_TRY(hipMemcpyAsync(ctx->host_scalars, dv, sizeof(double), hipMemcpyDeviceToHost, st));
+    BSM_HIP_TRY(hipStreamSynchronize(st));
+    return ctx->host_scalars[0];
+}
+
+}  // namespace bsm

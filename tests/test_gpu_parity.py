@@ -1,0 +1,337 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded inputs.
+
+Tolerances: patterns and flop counts bit-exact; single products, traces and
+inner products within 1e-12 of the result scale (only the summation order
+differs); Hotelling after 10 steps and LNV after 20 iterations within 1e-10
+relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bsm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_08941_amd as bsm
+    return bsm
+
+
+@pytest.fixture(scope="module")
+def ctx(bsm):
+    return bsm.Context(0)
+
+
+def gpat(bsm, ctx, pos, box, r, b):
+    return bsm.Pattern(ctx, torch.tensor(pos, dtype=torch.float64, device=ctx.device), box, r, b)
+
+
+def gmat(bsm, P, blocks):
+    return bsm.Matrix(P, torch.tensor(np.ascontiguousarray(blocks), dtype=torch.float64, device=P.ctx.device))
+
+
+def host(M):
+    torch.cuda.synchronize()
+    return M.blocks.cpu().numpy()
+
+
+def rel_err(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+SYSTEMS = {
+    "si64": lambda: synth.si64_b4(),
+    "si64_disp": lambda: synth.make_system("d", 2, 4, synth.SMALL_CUTOFFS, 3, displacement_sigma=0.2),
+    "ortho_2x3x4": lambda: synth.make_system("o", (2, 3, 4), 4, synth.SMALL_CUTOFFS, 4, displacement_sigma=0.05),
+    "si256_disp": lambda: synth.make_system("d2", (4, 4, 2), 4, synth.SMALL_CUTOFFS, 5, displacement_sigma=0.1),
+}
+
+
+# ------------------------------------------------------------------ patterns
+@pytest.mark.parametrize("name,cutoffs", [("si64", [3.0, 6.0, 8.0, 10.0, 14.0, 30.0]),
+                                          ("si64_disp", [4.0, 6.0, 7.3]),
+                                          ("ortho_2x3x4", [2.5, 6.0, 9.0, 16.0]),
+                                          ("si256_disp", [6.0, 8.0, 12.0])])
+def test_pattern_bitexact(bsm, ctx, name, cutoffs):
+    s = SYSTEMS[name]()
+    for r in cutoffs:
+        say(f"pattern {name} r={r}")
+        P = gpat(bsm, ctx, s.positions, s.box, r, 4)
+        rp, cols = P.to_host()
+        Po = O.create_pattern(s.positions, s.box, r)
+        assert np.array_equal(rp, Po.rowptr) and np.array_equal(cols, Po.cols), (name, r)
+        assert P.max_row == int(np.diff(Po.rowptr).max())
+
+
+@pytest.mark.parametrize("r", [6.0, 10.0, 16.0])
+def test_pattern_4096_bitexact(bsm, ctx, r):
+    pos, box, _ = synth.diamond_positions((8, 8, 8))
+    say(f"pattern 4096 r={r}")
+    P = gpat(bsm, ctx, pos, box, r, 9)
+    rp, cols = P.to_host()
+    Po = O.create_pattern(pos, box, r)
+    assert np.array_equal(rp, Po.rowptr) and np.array_equal(cols, Po.cols)
+
+
+def test_pattern_single_atom(bsm, ctx):
+    P = gpat(bsm, ctx, np.array([[1.0, 2.0, 3.0]]), (5.0, 5.0, 5.0), 2.0, 9)
+    rp, cols = P.to_host()
+    assert list(rp) == [0, 1] and list(cols) == [0]
+
+
+def test_pattern_rejects_bad_input(bsm, ctx):
+    pos = np.zeros((4, 3))
+    with pytest.raises(bsm.BSMError) as e:
+        gpat(bsm, ctx, pos, (5.0, 5.0, 5.0), -1.0, 4)
+    assert e.value.code == bsm.EINVAL
+    pos[1, 0] = np.nan
+    with pytest.raises(bsm.BSMError) as e:
+        gpat(bsm, ctx, pos, (5.0, 5.0, 5.0), 2.0, 4)
+    assert e.value.code == bsm.EINVAL
+
+
+# ------------------------------------------------------------------ products
+PRODUCT_CASES = [(6, 6, 8), (8, 6, 5), (3, 8, 6), (6, 8, 14), (12, 12, 12), (8, 8, 3)]
+
+
+@pytest.mark.parametrize("b", [1, 4, 9, 16])
+def test_product_parity(bsm, ctx, b):
+    s = SYSTEMS["si256_disp"]()
+    cut = sorted({r for case in PRODUCT_CASES for r in case})
+    gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in cut}
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in cut}
+    for n, (ra, rb, rc) in enumerate(PRODUCT_CASES):
+        say(f"product b={b} P{ra} x P{rb} -> P{rc}")
+        a = synth.random_blocks(op[ra].nnz, b, 10 + n)
+        bb = synth.random_blocks(op[rb].nnz, b, 20 + n)
+        c0 = synth.random_blocks(op[rc].nnz, b, 30 + n)
+        A, B, C = gmat(bsm, gp[ra], a), gmat(bsm, gp[rb], bb), gmat(bsm, gp[rc], c0)
+        bsm.multiply_truncate(0.75, A, B, -0.5, C)
+        Co = O.Matrix(op[rc], b, c0.copy())
+        O.multiply_truncate(0.75, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), -0.5, Co)
+        assert rel_err(host(C), Co.blocks) < 1e-12
+        # algorithmic flop count: 2 b^3 per block triple, bit-exact
+        tri = O.count_triples(op[ra], op[rb], op[rc]).sum()
+        assert bsm.product_flops(gp[ra], gp[rb], gp[rc]) == 2.0 * b ** 3 * tri
+
+
+def test_product_beta_zero_ignores_nan_and_is_deterministic(bsm, ctx):
+    s = SYSTEMS["si64"]()
+    P6, P8 = (gpat(bsm, ctx, s.positions, s.box, r, 4) for r in (6.0, 8.0))
+    o6, o8 = (O.create_pattern(s.positions, s.box, r) for r in (6.0, 8.0))
+    a = synth.random_blocks(o6.nnz, 4, 1)
+    A, B = gmat(bsm, P6, a), gmat(bsm, P6, a[::-1])
+    C = gmat(bsm, P8, np.full((o8.nnz, 4, 4), np.nan))
+    bsm.multiply_truncate(1.0, A, B, 0.0, C)
+    first = host(C).copy()
+    assert np.isfinite(first).all()
+    for _ in range(3):
+        bsm.multiply_truncate(1.0, A, B, 0.0, C)
+        assert np.array_equal(host(C), first)
+    want = O.product(O.Matrix(o6, 4, a), O.Matrix(o6, 4, a[::-1].copy()), o8)
+    assert rel_err(first, want.blocks) < 1e-13
+
+
+def test_product_errors(bsm, ctx):
+    s = SYSTEMS["si64"]()
+    P4 = gpat(bsm, ctx, s.positions, s.box, 6.0, 4)
+    P9 = gpat(bsm, ctx, s.positions, s.box, 6.0, 9)
+    A4, A9 = bsm.Matrix(P4), bsm.Matrix(P9)
+    with pytest.raises(bsm.BSMError) as e:
+        bsm.multiply_truncate(1.0, A4, A9, 0.0, bsm.Matrix(P4))
+    assert e.value.code == bsm.EPATTERN
+    with pytest.raises(bsm.BSMError) as e:
+        bsm.multiply_truncate(1.0, A4, A4, 0.0, A4)
+    assert e.value.code == bsm.EINVAL
+
+
+def test_fill_blocks_outside_pattern(bsm, ctx):
+    s = SYSTEMS["si64"]()
+    P3 = gpat(bsm, ctx, s.positions, s.box, 3.0, 4)
+    M = bsm.Matrix(P3)
+    with pytest.raises(bsm.BSMError) as e:
+        bsm.fill_blocks(M, s.S.rows, s.S.cols, s.S.blocks)   # S reaches 6 A
+    assert e.value.code == bsm.EPATTERN
+
+
+# ------------------------------------------------------------------ reductions and elementwise
+@pytest.mark.parametrize("ra,rb", [(6, 6), (6, 8), (3, 12), (8, 5)])
+def test_trace_parity(bsm, ctx, ra, rb):
+    s = SYSTEMS["si256_disp"]()
+    say(f"trace P{ra} . P{rb}")
+    ga, gb = gpat(bsm, ctx, s.positions, s.box, float(ra), 9), gpat(bsm, ctx, s.positions, s.box, float(rb), 9)
+    oa, ob = O.create_pattern(s.positions, s.box, float(ra)), O.create_pattern(s.positions, s.box, float(rb))
+    a, b = synth.random_blocks(oa.nnz, 9, 3), synth.random_blocks(ob.nnz, 9, 4)
+    want = O.trace_product(O.Matrix(oa, 9, a), O.Matrix(ob, 9, b))
+    scale = np.sqrt((a ** 2).sum() * (b ** 2).sum())
+    got = bsm.trace_product(gmat(bsm, ga, a), gmat(bsm, gb, b))
+    assert abs(got - want) <= 1e-13 * scale
+    assert bsm.trace_product(gmat(bsm, ga, a), gmat(bsm, gb, b)) == got   # bitwise reproducible
+
+
+def test_elementwise_parity(bsm, ctx):
+    s = SYSTEMS["si256_disp"]()
+    g6, g8 = gpat(bsm, ctx, s.positions, s.box, 6.0, 9), gpat(bsm, ctx, s.positions, s.box, 8.0, 9)
+    o6, o8 = O.create_pattern(s.positions, s.box, 6.0), O.create_pattern(s.positions, s.box, 8.0)
+    a, b = synth.random_blocks(o8.nnz, 9, 5), synth.random_blocks(o8.nnz, 9, 6)
+    X, Y = gmat(bsm, g8, a), gmat(bsm, g8, b)
+    assert abs(bsm.dot(X, Y) - O.dot(O.Matrix(o8, 9, a), O.Matrix(o8, 9, b))) <= 1e-12 * np.abs(a * b).sum()
+    bsm.axpby(2.5, X, -0.5, Y)
+    np.testing.assert_allclose(host(Y), 2.5 * a - 0.5 * b, rtol=1e-15, atol=1e-15)
+    bsm.symmetrize(X)
+    np.testing.assert_array_equal(host(X), O.symmetrize(O.Matrix(o8, 9, a)).blocks)
+    M6 = bsm.Matrix(g6)
+    bsm.mask_copy(X, M6)
+    np.testing.assert_array_equal(host(M6), O.mask_copy(O.symmetrize(O.Matrix(o8, 9, a)), o6).blocks)
+    M8 = bsm.Matrix(g8)
+    bsm.mask_copy(M6, M8)    # into a larger pattern: zero fill
+    np.testing.assert_array_equal(host(M8), O.mask_copy(O.Matrix(o6, 9, host(M6)), o8).blocks)
+    bsm.set_identity(M8, 0.25)
+    np.testing.assert_array_equal(host(M8), O.identity(o8, 9, 0.25).blocks)
+
+
+# ------------------------------------------------------------------ Hotelling
+def _load_SH(bsm, ctx, s):
+    P6 = gpat(bsm, ctx, s.positions, s.box, s.cutoffs["S"], s.b)
+    S, H = bsm.Matrix(P6), bsm.Matrix(P6)
+    bsm.fill_blocks(S, s.S.rows, s.S.cols, s.S.blocks)
+    bsm.fill_blocks(H, s.H.rows, s.H.cols, s.H.blocks)
+    o6 = O.create_pattern(s.positions, s.box, s.cutoffs["S"])
+    oS = O.from_blocks(o6, s.b, s.S.rows, s.S.cols, s.S.blocks)
+    oH = O.from_blocks(o6, s.b, s.H.rows, s.H.cols, s.H.blocks)
+    assert np.array_equal(host(S), oS.blocks) and np.array_equal(host(H), oH.blocks)
+    return S, H, oS, oH
+
+
+@pytest.mark.parametrize("b", [4, 9])
+def test_hotelling_parity_small(bsm, ctx, b):
+    s = synth.make_system("h", 2, b, synth.SMALL_CUTOFFS, 2205)
+    say(f"hotelling 64 atoms b={b}")
+    S, _, oS, _ = _load_SH(bsm, ctx, s)
+    PZ = gpat(bsm, ctx, s.positions, s.box, 8.0, b)
+    Z = bsm.Matrix(PZ)
+    r = bsm.hotelling_inverse(S, Z, max_iter=10, tol=0.0)
+    ro = O.hotelling_inverse(oS, O.create_pattern(s.positions, s.box, 8.0), max_iter=10, tol=0.0)
+    assert r.status == ro.status == 0 and r.iterations == ro.iterations
+    assert r.alpha == pytest.approx(ro.alpha, rel=1e-14)   # row sums in another order
+    np.testing.assert_allclose(r.residuals, ro.residuals, rtol=1e-10, atol=1e-12)
+    assert rel_err(host(Z), ro.Z.blocks) < 1e-10
+
+
+def test_hotelling_untruncated_converges_to_inverse(bsm, ctx):
+    s = synth.si64_b4()
+    S, _, oS, _ = _load_SH(bsm, ctx, s)
+    Z = bsm.Matrix(gpat(bsm, ctx, s.positions, s.box, 30.0, 4))
+    r = bsm.hotelling_inverse(S, Z, max_iter=60, tol=1e-12)
+    assert r.status == 0
+    Zd = O.Matrix(O.create_pattern(s.positions, s.box, 30.0), 4, host(Z)).to_dense()
+    np.testing.assert_allclose(Zd, np.linalg.inv(oS.to_dense()), atol=1e-12)
+
+
+def test_hotelling_failures(bsm, ctx):
+    bad = synth.make_system("bad", 2, 4, synth.SMALL_CUTOFFS, 2205, s_amp=3.0)
+    S, _, oS, _ = _load_SH(bsm, ctx, bad)
+    Z = bsm.Matrix(gpat(bsm, ctx, bad.positions, bad.box, 8.0, 4))
+    r = bsm.hotelling_inverse(S, Z, max_iter=200, tol=1e-12, raise_on_error=False)
+    assert r.status == bsm.EDIVERGED
+    s = synth.si64_b4()
+    S, _, _, _ = _load_SH(bsm, ctx, s)
+    S.blocks[7, 1, 2] = float("nan")
+    r = bsm.hotelling_inverse(S, Z, max_iter=5, tol=1e-12, raise_on_error=False)
+    assert r.status == bsm.ENONFINITE
+
+
+# ------------------------------------------------------------------ LNV
+def _lnv_pair(bsm, ctx, s, mode=0, mu=0.0, rl=None, rz=None, hot_iter=10, tol_E=1e-8):
+    rl = s.cutoffs["L"] if rl is None else rl
+    rz = s.cutoffs["Z"] if rz is None else rz
+    S, H, oS, oH = _load_SH(bsm, ctx, s)
+    Z = bsm.Matrix(gpat(bsm, ctx, s.positions, s.box, rz, s.b))
+    bsm.hotelling_inverse(S, Z, max_iter=hot_iter, tol=0.0)
+    L = bsm.Matrix(gpat(bsm, ctx, s.positions, s.box, rl, s.b))
+    g = bsm.LNV(S, H, Z, L, s.n_electrons, mode=mode, mu=mu, tol_E=tol_E)
+    oz = O.hotelling_inverse(oS, O.create_pattern(s.positions, s.box, rz), max_iter=hot_iter, tol=0.0).Z
+    st = O.lnv_init(oS, oH, oz, O.create_pattern(s.positions, s.box, rl), s.n_electrons, mode=mode, mu=mu,
+                    tol_E=tol_E)
+    assert rel_err(host(L), st.L.blocks) < 1e-12
+    return g, L, st
+
+
+@pytest.mark.parametrize("b", [4, 9])
+def test_lnv_parity_20_iterations(bsm, ctx, b):
+    s = synth.make_system("l", 2, b, synth.SMALL_CUTOFFS, 2205)
+    say(f"lnv 64 atoms b={b}")
+    g, L, st = _lnv_pair(bsm, ctx, s)
+    for it in range(20):
+        rg, ro = g.step(), O.lnv_step(st)
+        assert rg.status == ro.status == 0
+        assert abs(rg.E - ro.E) <= 1e-10 * abs(ro.E), (it, rg.E, ro.E)
+        assert abs(rg.N - ro.N) <= 1e-10 * abs(ro.N)
+        if it < 6:   # later, c1 is a small difference of O(10) traces and alpha carries its rounding
+            assert abs(rg.alpha - ro.alpha) <= 1e-6 * abs(ro.alpha), (it, rg.alpha, ro.alpha)
+    Lg, Lo = host(L), st.L.blocks
+    assert np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo) < 1e-8
+    assert rg.product_flops > 0
+
+
+def test_lnv_bond_projector_closed_form(bsm, ctx):
+    s = synth.make_system("bond", 2, 9, synth.SMALL_CUTOFFS, 5, s_amp=0.0, h_random=False)
+    g, L, st = _lnv_pair(bsm, ctx, s, tol_E=1e-12)
+    for _ in range(60):
+        r = g.step()
+        if r.converged:
+            break
+    assert abs(r.E - (-4 * 64 * synth.T_BOND)) < 1e-9
+
+
+def test_lnv_grand_and_runaway(bsm, ctx):
+    s = synth.si64_b4()
+    g, L, st = _lnv_pair(bsm, ctx, s, mode=1, mu=0.0)
+    om = [g.step().Omega for _ in range(8)]
+    assert all(b < a for a, b in zip(om, om[1:]))
+    # L = 2 Z with mu far below the spectrum: no minimum along the line
+    S, H, oS, oH = _load_SH(bsm, ctx, s)
+    Z = bsm.Matrix(gpat(bsm, ctx, s.positions, s.box, 8.0, 4))
+    bsm.hotelling_inverse(S, Z, max_iter=10, tol=0.0)
+    L = bsm.Matrix(Z.pattern, 2.0 * Z.blocks.clone())
+    g = bsm.LNV(S, H, Z, L, s.n_electrons, mode=1, mu=-10.0, init_from_z=False)
+    assert g.step().status == bsm.ERUNAWAY
+
+
+# ------------------------------------------------------------------ 4096 atoms, 9 orbitals
+def test_w_class_product_4096_sampled(bsm, ctx):
+    """The 16 A x 16 A -> 16 A product at full size, in the launch the benchmark
+    times; sampled output rows checked against the oracle."""
+    pos, box, _ = synth.diamond_positions((8, 8, 8))
+    say("W-class 4096 atoms b=9: patterns")
+    P16 = gpat(bsm, ctx, pos, box, 16.0, 9)
+    o16 = O.create_pattern(pos, box, 16.0)
+    rng = np.random.default_rng(2205)
+    x = rng.uniform(-1, 1, (o16.nnz, 9, 9))
+    y = rng.uniform(-1, 1, (o16.nnz, 9, 9))
+    say("W-class 4096 atoms b=9: GPU product")
+    X, Y = gmat(bsm, P16, x), gmat(bsm, P16, y)
+    C = bsm.Matrix(P16)
+    bsm.multiply_truncate(1.0, X, Y, 0.0, C)
+    assert bsm.product_flops(P16, P16, P16) == 2.0 * 729 * O.count_triples(o16, o16, o16).sum()
+    g = host(C)
+    rows = [0, 1, 7, 1000, 2047, 4095]
+    say("W-class 4096 atoms b=9: oracle rows", rows)
+    Co = O.Matrix(o16, 9)
+    for r in rows:
+        O.multiply_truncate(1.0, O.Matrix(o16, 9, x), O.Matrix(o16, 9, y), 0.0, Co, r, r + 1)
+        sl = slice(o16.rowptr[r], o16.rowptr[r + 1])
+        assert rel_err(g[sl], Co.blocks[sl]) < 1e-12, r

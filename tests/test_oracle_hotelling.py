@@ -25,9 +25,8 @@ def test_untruncated_closed_form(si64):
     a = res.alpha
     assert a == pytest.approx(1.0 / np.abs(S.to_dense()).sum(1).max(), rel=1e-15)
     for n, r in enumerate(res.residuals):
-        want2 = np.sum((1.0 - a * lam) ** (2 ** (n + 1)))
-        # the trace form N_b - 2 Tr T + ||T||^2 cancels to ~1e-13 N_b absolute in r^2
-        assert abs(r * r - want2) <= 1e-8 * want2 + 1e-13 * len(lam)
+        want = math.sqrt(np.sum((1.0 - a * lam) ** (2 ** (n + 1))))
+        assert r == pytest.approx(want, rel=1e-8, abs=1e-13)
     np.testing.assert_allclose(res.Z.to_dense(), np.linalg.inv(S.to_dense()), atol=1e-12)
 
 
