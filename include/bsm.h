@@ -115,6 +115,17 @@ typedef struct {
     double ms;           /* summed event time, milliseconds */
 } bsm_product_stat;
 
+/* Rows of C per wavefront tile in product plans built from now on: 2, 4 or 8
+ * (0 restores the default for the orbital count).  Larger values reuse each B
+ * block across more rows at the cost of idle lanes.  Clears cached plans. */
+int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
+/* FP64 product kernel of plans built from now on: 0 = the uniform A block read
+ * through the scalar cache into SGPRs; 1 = A held in VGPRs and broadcast by DPP
+ * (b = 4 and 9, rows per wave 2 or 4; other shapes use 0).  Variant 1 multiplies
+ * absent (k, j) blocks by zero instead of skipping them, so a non-finite block
+ * of A can make other blocks of its output row non-finite.  Clears cached plans. */
+int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant);
+
 /* enable != 0 clears the statistics and starts recording; 0 stops. */
 int bsm_ctx_set_profiling(bsm_ctx ctx, int enable);
 /* Synchronises the stream, then writes up to `max` classes (most time first)

@@ -86,6 +86,8 @@ EXPORTS = {
     "bsm_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
     "bsm_last_error": (ctypes.c_char_p, []),
     "bsm_ctx_set_profiling": (c_int, [c_void_p, c_int]),
+    "bsm_ctx_set_rows_per_wave": (c_int, [c_void_p, c_int]),
+    "bsm_ctx_set_product_variant": (c_int, [c_void_p, c_int]),
     "bsm_ctx_product_stats": (c_int, [c_void_p, ctypes.POINTER(_ProductStat), c_int, ctypes.POINTER(c_int)]),
     "bsm_create_pattern": (c_int, [c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_double), c_double,
                                    ctypes.POINTER(c_void_p)]),
@@ -173,6 +175,14 @@ class Context:
     def set_profiling(self, enable: bool) -> None:
         """Time every product launch with HIP events on this context's stream."""
         _check(_lib.bsm_ctx_set_profiling(self.handle, int(bool(enable))))
+
+    def set_rows_per_wave(self, rows: int) -> None:
+        """Rows per wavefront tile (2, 4, 8; 0 = default) of plans built from now on."""
+        _check(_lib.bsm_ctx_set_rows_per_wave(self.handle, int(rows)))
+
+    def set_product_variant(self, variant: int) -> None:
+        """FP64 product kernel of plans built from now on (0: SGPR A, 1: DPP-broadcast A)."""
+        _check(_lib.bsm_ctx_set_product_variant(self.handle, int(variant)))
 
     def product_stats(self) -> list:
         """Per (P_A, P_B, P_C) class: launches, algorithmic flops, event milliseconds."""

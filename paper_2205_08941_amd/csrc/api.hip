@@ -61,17 +61,16 @@ void Context::clear_profile()
     prof.clear();
 }
 
-void Context::forget_pattern(uint64_t id)
+void Context::retire_profile(const std::function<bool(const Plan *)> &pick)
 {
-    // recorded launches of plans about to be dropped are folded away first
     bool touched = false;
     for (auto &r : prof)
-        if (r.plan->ids[0] == id || r.plan->ids[1] == id || r.plan->ids[2] == id) touched = true;
+        if (pick(r.plan)) touched = true;
     if (touched) {
         (void)hipStreamSynchronize(stream);
         std::vector<ProfRec> keep;
         for (auto &r : prof) {
-            if (r.plan->ids[0] == id || r.plan->ids[1] == id || r.plan->ids[2] == id) {
+            if (pick(r.plan)) {
                 float ms = 0.f;
                 (void)hipEventElapsedTime(&ms, r.start, r.stop);
                 auto &acc = retired[std::make_tuple(r.plan->natoms, r.plan->b, r.plan->cutoffs[0],
@@ -87,6 +86,12 @@ void Context::forget_pattern(uint64_t id)
         }
         prof.swap(keep);
     }
+}
+
+void Context::forget_pattern(uint64_t id)
+{
+    // recorded launches of plans about to be dropped are folded away first
+    retire_profile([id](const Plan *p) { return p->ids[0] == id || p->ids[1] == id || p->ids[2] == id; });
     for (auto it = plans.begin(); it != plans.end();) {
         if (std::get<0>(it->first) == id || std::get<1>(it->first) == id || std::get<2>(it->first) == id)
             it = plans.erase(it);
@@ -174,6 +179,8 @@ int bsm_ctx_create(int device, void *hip_stream, bsm_alloc_fn alloc, bsm_free_fn
     c->c.user = user;
     c->c.red_partials = DevBuf(&c->c, sizeof(double) * ((size_t)kRedSlots * kRedBlocks + kRedSlots + 8));
     c->c.err_flag = DevBuf(&c->c, 256);
+    c->c.zero_block = DevBuf(&c->c, sizeof(double) * 256);
+    BSM_HIP_TRY(hipMemset(c->c.zero_block.ptr, 0, sizeof(double) * 256));
     BSM_HIP_TRY(hipHostMalloc((void **)&c->c.host_scalars, sizeof(double) * 64, hipHostMallocDefault));
     *out = c.release();
     return BSM_OK;
@@ -196,6 +203,33 @@ int bsm_ctx_destroy(bsm_ctx ctx)
     ctx->c.plans.clear();
     if (ctx->c.host_scalars) (void)hipHostFree(ctx->c.host_scalars);
     delete ctx;
+    return BSM_OK;
+    BSM_API_END
+}
+
+int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
+    BSM_REQUIRE(rows == 0 || rows == 2 || rows == 4 || rows == 8, BSM_EINVAL, "rows must be 0, 2, 4 or 8");
+    BSM_HIP_TRY(hipStreamSynchronize(ctx->c.stream));
+    // timing records point at plans: fold them away before the plans go
+    ctx->c.retire_profile([](const Plan *) { return true; });
+    ctx->c.plans.clear();
+    ctx->c.rows_per_wave = rows;
+    return BSM_OK;
+    BSM_API_END
+}
+
+int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
+    BSM_REQUIRE(variant == 0 || variant == 1, BSM_EINVAL, "variant must be 0 or 1");
+    BSM_HIP_TRY(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.retire_profile([](const Plan *) { return true; });
+    ctx->c.plans.clear();
+    ctx->c.product_variant = variant;
     return BSM_OK;
     BSM_API_END
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -52,15 +53,21 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
-// Product plan: one work tile per (row i of C, run of up to `jt` consecutive
-// blocks of that row).  Cached per (P_A, P_B, P_C).
+// Product plan for C = mask_{P_C}(A B): tiles of (G rows, up to jt output
+// columns) and, per tile, the list of k with the slots of A_{i_a k} and B_kj.
+// Built on the GPU on first use, cached per (P_A, P_B, P_C).
 struct Plan {
     uint64_t ids[3] = {0, 0, 0};
     double cutoffs[3] = {0, 0, 0};
     int natoms = 0, b = 0;
-    int jt = 0;                 // output blocks per wavefront tile
+    int G = 0;                  // rows per wavefront tile
+    int variant = 0;            // 0: A through SGPRs, 1: A in VGPRs with DPP broadcast
+    int jt = 0;                 // output block columns per wavefront tile (64 / b)
     int64_t ntiles = 0;
-    DevBuf tiles;               // int2 {row, first slot}
+    int64_t nentries = 0;
+    DevBuf hdr;                 // int [ntiles][G + G*jt]: rows, C slots
+    DevBuf ebeg;                // int64 [ntiles + 1]: entry ranges
+    DevBuf ent;                 // int [nentries][G + jt]: A slots, B slots
     double flops = 0.0;         // algorithmic: 2 b^3 per block triple
     int64_t triples = 0;
 };
@@ -73,12 +80,15 @@ class Context {
     bsm_free_fn free_fn = nullptr;
     void *user = nullptr;
     uint64_t next_pattern_id = 1;
+    int rows_per_wave = 0;      // product plans: 0 = per-b default, else 2, 4 or 8
+    int product_variant = 0;    // product kernel variant of plans built from now on
     // derived patterns (same atoms, another cutoff), owned here, keyed by (source id, cutoff)
     std::map<std::pair<uint64_t, double>, bsm_pattern_s *> derived;
     std::map<std::tuple<uint64_t, uint64_t, uint64_t>, std::unique_ptr<Plan>> plans;
     // reduction scratch
     DevBuf red_partials;        // double[kRedBlocks * kRedSlots]
     DevBuf err_flag;            // int
+    DevBuf zero_block;          // 16 x 16 FP64 zeros (absent B blocks in the DPP product)
     double *host_scalars = nullptr;  // pinned host, kRedSlots doubles
     // product timing (bsm_ctx_set_profiling)
     struct ProfRec {
@@ -96,6 +106,8 @@ class Context {
     std::map<std::tuple<int, int, double, double, double>, ProfAcc> retired;
     hipEvent_t take_event();
     void clear_profile();
+    // fold timing records of the picked plans into `retired` (they are about to go)
+    void retire_profile(const std::function<bool(const Plan *)> &pick);
 
     void *allocate(size_t bytes);
     void release(void *p);
@@ -141,9 +153,9 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
 void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
                         const double *A, const bsm_pattern_s *PB, const double *B, double beta,
                         const bsm_pattern_s *PC, double *C);
-int64_t count_triples(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB,
-                      const bsm_pattern_s *PC, const Plan *plan);
-void build_tiles(Context *ctx, const bsm_pattern_s *PC, Plan *plan);
+void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
+                Plan *plan, int G);
+int default_rows_per_wave(int b);
 
 // Traces of products Tr(A_n B_n) for up to kRedSlots pairs in one pass; A_n all
 // on one pattern, B_n all on one pattern.  Results to host `out`.  Synchronises.

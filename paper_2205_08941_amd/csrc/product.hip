@@ -5,20 +5,27 @@
 // and Current Status) and the part it already started to move to GPUs
 // (Meeting the Exascale Challenges).
 //
-// Work decomposition (gfx950, wave64):
-//   * a tile is one output row i and a run of JT consecutive blocks (i, j) of
-//     that row of P_C; one wavefront owns one tile;
-//   * lane l holds column c = l % b of output block j = l / b (JT = 64 / b
-//     blocks per wave: 7 for b = 9, 16 for b = 4) and keeps that column's b
-//     rows in registers for the whole contraction;
-//   * the wave walks k over row i of A in ascending order (uniform), so the
-//     b x b block A_ik has a wave-uniform address and is read through the
-//     scalar cache into SGPRs, broadcast to every lane as an FMA operand;
-//   * each lane walks column j of B (= row j of the symmetric pattern) with its
-//     own merge pointer and takes part only when (k, j) is in P_B.  Only block
-//     triples (i, k, j) that exist are multiplied: no zero fill, and the k-sum
-//     of every output runs in ascending k (deterministic).
+// Work decomposition (gfx950, wave64, FP64 vector FMA):
+//   * atoms are taken G at a time as a row group; the union of the group's
+//     rows of P_C is cut into runs of JT = 64 / b columns.  A tile is (row
+//     group, run); one wavefront owns one tile;
+//   * lane l holds column c = l % b of the output blocks (i_a, j), j = run[l / b],
+//     for all G rows i_a of the group: G x b FP64 accumulators per lane;
+//   * the plan lists, per tile, every k for which some (i_a, k, j) triple
+//     exists, with the slots of A_{i_a k} and B_kj.  The wave walks that list:
+//     it loads the b x b block A_{i_a k} at a wave-uniform address through the
+//     scalar cache (an SGPR operand broadcast to all lanes), each lane loads its
+//     column of B_kj once and uses it for all G rows.  Exec masks drop lanes
+//     whose (k, j) or (i_a, j) is absent, so only existing triples are summed,
+//     in ascending k (deterministic);
+//   * the next list entry and its B columns are loaded while the current one
+//     is multiplied; tiles are mapped so that each XCD owns a contiguous range
+//     of row groups (neighbouring rows share A and B blocks in its L2).
+// No zero fill enters the flop count: 2 b^3 per triple (i, k, j) present.
 #include "bsm_internal.h"
+
+#include <algorithm>
+#include <utility>
 
 namespace bsm {
 namespace {
@@ -27,130 +34,482 @@ namespace {
 // address is uniform.
 template <class T> using const_as4 = const __attribute__((address_space(4))) T;
 
-template <int B> struct Tile {
-    static constexpr int JT = 64 / B;
-};
+constexpr int kXcd = 8;       // MI355X: 8 XCDs, workgroups dealt round-robin
+constexpr int kWaves = 4;     // wavefronts (tiles) per workgroup
 
-template <int B>
-__global__ __launch_bounds__(256) void k_product_f64(
-    const int2 *__restrict__ tiles, int64_t ntiles,
-    const int *__restrict__ rpA, const int *__restrict__ cA, const double *__restrict__ vA,
-    const int *__restrict__ rpB, const int *__restrict__ cB, const int *__restrict__ tmB,
-    const double *__restrict__ vB,
-    const int *__restrict__ rpC, const int *__restrict__ cC, double *__restrict__ vC,
-    double alpha, double beta)
+__device__ inline int64_t logical_workgroup(int64_t nwg_padded)
 {
-    constexpr int JT = Tile<B>::JT;
-    constexpr int BB = B * B;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (wave >= ntiles) return;
-    const int lane = threadIdx.x & 63;
-    const int2 t = tiles[wave];
-    const int i = __builtin_amdgcn_readfirstlane(t.x);
-    const int s0 = __builtin_amdgcn_readfirstlane(t.y);
-    const int send = rpC[i + 1];
-    const int jl = lane / B, c = lane - jl * B;
-    const int sC = s0 + jl;
-    const bool valid = (jl < JT) && (sC < send);
-    int p = 0, pend = 0;
-    if (valid) {
-        const int j = cC[sC];
-        p = rpB[j];
-        pend = rpB[j + 1];
-    }
-    double acc[B];
-#pragma unroll
-    for (int r = 0; r < B; ++r) acc[r] = 0.0;
+    const int64_t w = blockIdx.x;
+    const int64_t per = nwg_padded / kXcd;
+    return (w % kXcd) * per + w / kXcd;
+}
 
-    const int a0 = __builtin_amdgcn_readfirstlane(rpA[i]);
-    const int a1 = __builtin_amdgcn_readfirstlane(rpA[i + 1]);
-    const_as4<int> *cAu = (const_as4<int> *)cA;
-    const_as4<double> *vAu = (const_as4<double> *)vA;
-    for (int sa = a0; sa < a1; ++sa) {
-        const int k = cAu[sa];
-        while (p < pend && cB[p] < k) ++p;
-        const bool act = (p < pend) && (cB[p] == k);
-        if (__builtin_amdgcn_ballot_w64(act) == 0) continue;
-        if (act) {
-            const double *bp = vB + (int64_t)tmB[p] * BB + c;
-            double bv[B];
+// Tile header, ints: rows[G] (atom ids, -1 = padding), cslot[G][JT] (slot of
+// (i_a, j) in C or -1).  Entries of tile t: ebeg[t] .. ebeg[t+1], each G + JT
+// ints: aslot[G] (slot of (i_a, k) in A or -1), bslot[JT] (slot of (k, j) in B or -1).
+template <int B, int G>
+__device__ inline void multiply_entry(const_as4<int> *entu, int64_t q, const_as4<double> *vAu, const double (&bv)[B],
+                                      bool bact, const bool (&cact)[G], double (&acc)[G][B])
+{
+    constexpr int BB = B * B;
+    constexpr int ES = G + 64 / B;
 #pragma unroll
-            for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
-            const_as4<double> *ap = vAu + (int64_t)sa * BB;
+    for (int a = 0; a < G; ++a) {
+        const int as = entu[q * ES + a];
+        if (as < 0) continue;
+        if (bact && cact[a]) {
+            const_as4<double> *ap = vAu + (int64_t)as * BB;
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
+            for (int r = 0; r < B; ++r)
 #pragma unroll
-                for (int m = 0; m < B; ++m) acc[r] = fma(ap[r * B + m], bv[m], acc[r]);
-            }
+                for (int m = 0; m < B; ++m) acc[a][r] = fma(ap[r * B + m], bv[m], acc[a][r]);
         }
     }
-    if (valid) {
-        double *cp = vC + (int64_t)sC * BB + c;
+}
+
+// Tile header, ints: rows[G] (atom ids, -1 = padding), cslot[G][JT] (slot of
+// (i_a, j) in C or -1).  Entries of tile t: ebeg[t] .. ebeg[t+1] (an even count;
+// an odd list ends in a padding entry whose A slots are all -1), each G + JT
+// ints: aslot[G] (slot of (i_a, k) in A or -1), bslot[JT] (slot of (k, j) in B
+// or -1).  The entry array has 4 spare entries at its end, so the index
+// prefetch past a tile's last entry stays in bounds.
+template <int B, int G>
+__global__ __launch_bounds__(256) void k_product_f64(
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
+    const int *__restrict__ ent, const double *__restrict__ vA, const double *__restrict__ vB,
+    double *__restrict__ vC, double alpha, double beta)
+{
+    constexpr int JT = 64 / B;
+    constexpr int BB = B * B;
+    constexpr int HS = G + G * JT;
+    constexpr int ES = G + JT;
+    const int64_t tile = logical_workgroup(nwg_padded) * kWaves + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const int jl0 = lane / B, c = lane - jl0 * B;
+    const bool lane_ok = jl0 < JT;
+    const int jl = lane_ok ? jl0 : JT - 1;     // spare lanes read a valid column and stay masked
+    const int *h = hdr + tile * HS;
+    int cs[G];
+    bool cact[G];
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        cs[a] = lane_ok ? h[G + a * JT + jl] : -1;
+        cact[a] = cs[a] >= 0;
+    }
+    double acc[G][B];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int r = 0; r < B; ++r) acc[a][r] = 0.0;
+
+    const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
+    const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
+    const int n = (int)(e1 - e0);                  // even
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
+    const int *entv = ent + e0 * ES + G + jl;      // this lane's B slot column
+    const_as4<double> *vAu = (const_as4<double> *)vA;
+    const double *vBc = vB + c;
+
+    // ping-pong buffers: entry q in ba while q+1 loads into bb, then q+1 in bb
+    // while q+2 loads into ba; B slot indices run two entries ahead.
+    double ba[B], bb[B];
+    int ia = entv[0], ib = entv[ES];
+    ia = (0 < n) ? ia : -1;
+    ib = (1 < n) ? ib : -1;
+    {
+        const double *bp = vBc + (int64_t)max(ia, 0) * BB;
+#pragma unroll
+        for (int m = 0; m < B; ++m) ba[m] = bp[m * B];
+    }
+    for (int q = 0; q < n; q += 2) {
+        int ic = entv[(int64_t)(q + 2) * ES];
+        ic = (q + 2 < n) ? ic : -1;
+        {
+            const double *bp = vBc + (int64_t)max(ib, 0) * BB;
+#pragma unroll
+            for (int m = 0; m < B; ++m) bb[m] = bp[m * B];
+        }
+        multiply_entry<B, G>(entu, q, vAu, ba, ia >= 0, cact, acc);
+        int id = entv[(int64_t)(q + 3) * ES];
+        id = (q + 3 < n) ? id : -1;
+        {
+            const double *bp = vBc + (int64_t)max(ic, 0) * BB;
+#pragma unroll
+            for (int m = 0; m < B; ++m) ba[m] = bp[m * B];
+        }
+        multiply_entry<B, G>(entu, q + 1, vAu, bb, ib >= 0, cact, acc);
+        ia = ic;
+        ib = id;
+    }
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (!cact[a]) continue;
+        double *cp = vC + (int64_t)cs[a] * BB + c;
         if (beta == 0.0) {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[r];
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[r] + beta * cp[r * B];
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
         }
     }
 }
 
-// Same walk as the product, counting the block triples each lane takes part in.
+// ---------------------------------------------------------------- DPP variant
+// The same tiles and entry lists, with the uniform operand A_{i_a k} held in
+// VGPRs instead of SGPRs: lane l of every row of 16 lanes holds elements
+// l % 16 + 16 v (v < NA) of the block, loaded with ordinary pipelined vector
+// loads, and each FMA takes its A element by a DPP row broadcast
+// (row_newbcast: lane n of each 16-lane row to the whole row).  This removes
+// the scalar-load round trips of the SGPR variant from the inner loop.
+// One output row r of a block product: acc += sum_m A[r][m] * b[m], A[r][m]
+// broadcast from lane (r*b + m) % 16 of register (r*b + m) / 16.  The row's
+// FMAs form one asm block that starts with two wait states: a VALU write of a
+// register followed by a DPP read of it needs them, and the compiler does not
+// track that hazard into inline asm.
+#define BSM_FMA_DPP(acc, a, bq, lane) "v_fmac_f64_dpp " acc ", " a ", " bq " row_newbcast:" lane " row_mask:0xf bank_mask:0xf\n"
+
+template <int B, int NA, int R> struct DppRow;
+
+template <int NA, int R> struct DppRow<9, NA, R> {
+    static constexpr int e(int m) { return R * 9 + m; }
+    __device__ static inline void run(double &acc, const double (&av)[NA], const double (&bv)[9])
+    {
+        asm("s_nop 1\n"
+            BSM_FMA_DPP("%0", "%1", "%10", "%19") BSM_FMA_DPP("%0", "%2", "%11", "%20")
+            BSM_FMA_DPP("%0", "%3", "%12", "%21") BSM_FMA_DPP("%0", "%4", "%13", "%22")
+            BSM_FMA_DPP("%0", "%5", "%14", "%23") BSM_FMA_DPP("%0", "%6", "%15", "%24")
+            BSM_FMA_DPP("%0", "%7", "%16", "%25") BSM_FMA_DPP("%0", "%8", "%17", "%26")
+            BSM_FMA_DPP("%0", "%9", "%18", "%27")
+            : "+v"(acc)
+            : "v"(av[e(0) >> 4]), "v"(av[e(1) >> 4]), "v"(av[e(2) >> 4]), "v"(av[e(3) >> 4]),
+              "v"(av[e(4) >> 4]), "v"(av[e(5) >> 4]), "v"(av[e(6) >> 4]), "v"(av[e(7) >> 4]),
+              "v"(av[e(8) >> 4]),
+              "v"(bv[0]), "v"(bv[1]), "v"(bv[2]), "v"(bv[3]), "v"(bv[4]), "v"(bv[5]), "v"(bv[6]), "v"(bv[7]),
+              "v"(bv[8]),
+              "n"(e(0) & 15), "n"(e(1) & 15), "n"(e(2) & 15), "n"(e(3) & 15), "n"(e(4) & 15), "n"(e(5) & 15),
+              "n"(e(6) & 15), "n"(e(7) & 15), "n"(e(8) & 15));
+    }
+};
+
+template <int NA, int R> struct DppRow<4, NA, R> {
+    static constexpr int e(int m) { return R * 4 + m; }
+    __device__ static inline void run(double &acc, const double (&av)[NA], const double (&bv)[4])
+    {
+        asm("s_nop 1\n"
+            BSM_FMA_DPP("%0", "%1", "%5", "%9") BSM_FMA_DPP("%0", "%2", "%6", "%10")
+            BSM_FMA_DPP("%0", "%3", "%7", "%11") BSM_FMA_DPP("%0", "%4", "%8", "%12")
+            : "+v"(acc)
+            : "v"(av[e(0) >> 4]), "v"(av[e(1) >> 4]), "v"(av[e(2) >> 4]), "v"(av[e(3) >> 4]),
+              "v"(bv[0]), "v"(bv[1]), "v"(bv[2]), "v"(bv[3]),
+              "n"(e(0) & 15), "n"(e(1) & 15), "n"(e(2) & 15), "n"(e(3) & 15));
+    }
+};
+#undef BSM_FMA_DPP
+
+template <int B, int NA, int... R>
+__device__ inline void fma_block(double (&acc)[B], const double (&av)[NA], const double (&bv)[B],
+                                 std::integer_sequence<int, R...>)
+{
+    (DppRow<B, NA, R>::run(acc[R], av, bv), ...);
+}
+
+// Element l16 + 16 v of the block into register v; indices past the block wrap
+// to its start (unused lanes, kept lane-varying so every element arrives by a
+// vector load straight into its VGPR).
+template <int B, int NA>
+__device__ inline void load_a(double (&av)[NA], const double *__restrict__ vA, int slot, int l16)
+{
+    constexpr int BB = B * B;
+    const double *ap = vA + (int64_t)max(slot, 0) * BB;
+#pragma unroll
+    for (int v = 0; v < NA; ++v) {
+        int idx = l16 + 16 * v;
+        if (idx >= BB) idx -= BB;
+        av[v] = ap[idx];
+    }
+}
+
+// Lanes whose (k, j) block is absent read a block of zeros instead: the DPP
+// broadcast needs every lane of the wave active (a read from an exec-disabled
+// source lane is invalid), so absent triples are multiplied by zero rather than
+// masked off.
 template <int B>
-__global__ __launch_bounds__(256) void k_count_triples(
-    const int2 *__restrict__ tiles, int64_t ntiles, const int *__restrict__ rpA,
-    const int *__restrict__ cA, const int *__restrict__ rpB, const int *__restrict__ cB,
-    const int *__restrict__ rpC, const int *__restrict__ cC, unsigned long long *__restrict__ total)
+__device__ inline void load_b(double (&bv)[B], const double *__restrict__ vBc, const double *__restrict__ zc, int slot)
 {
-    constexpr int JT = Tile<B>::JT;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (wave >= ntiles) return;
+    const double *bp = (slot >= 0) ? vBc + (int64_t)slot * (B * B) : zc;
+#pragma unroll
+    for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
+}
+
+template <int B, int G, int NA>
+__device__ inline void dpp_entry(const int (&as)[G], const double (&av)[G][NA], const double (&bv)[B],
+                                 double (&acc)[G][B])
+{
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (as[a] < 0) continue;   // wave-uniform
+        fma_block<B, NA>(acc[a], av[a], bv, std::make_integer_sequence<int, B>{});
+    }
+}
+
+template <int B, int G>
+__global__ __launch_bounds__(256) void k_product_f64_dpp(
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
+    const int *__restrict__ ent, const double *__restrict__ vA, const double *__restrict__ vB,
+    const double *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta)
+{
+    constexpr int JT = 64 / B;
+    constexpr int BB = B * B;
+    constexpr int NA = (BB + 15) / 16;
+    constexpr int HS = G + G * JT;
+    constexpr int ES = G + JT;
+    const int64_t tile = logical_workgroup(nwg_padded) * kWaves + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
     const int lane = threadIdx.x & 63;
-    const int2 t = tiles[wave];
-    const int i = t.x, s0 = t.y;
-    const int jl = lane / B, c = lane - jl * B;
-    const int sC = s0 + jl;
-    const bool valid = (jl < JT) && (sC < rpC[i + 1]) && (c == 0);
-    long long cnt = 0;
-    if (valid) {
-        const int j = cC[sC];
-        int p = rpB[j], pend = rpB[j + 1];
-        for (int sa = rpA[i]; sa < rpA[i + 1]; ++sa) {
-            const int k = cA[sa];
-            while (p < pend && cB[p] < k) ++p;
-            if (p < pend && cB[p] == k) ++cnt;
+    const int l16 = lane & 15;
+    const int jl0 = lane / B, c = lane - jl0 * B;
+    const bool lane_ok = jl0 < JT;
+    const int jl = lane_ok ? jl0 : JT - 1;
+    const int *h = hdr + tile * HS;
+    int cs[G];
+    bool cact[G];
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        cs[a] = lane_ok ? h[G + a * JT + jl] : -1;
+        cact[a] = cs[a] >= 0;
+    }
+    double acc[G][B];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int r = 0; r < B; ++r) acc[a][r] = 0.0;
+
+    const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
+    const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
+    const int n = (int)(e1 - e0);                  // even
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
+    const int *entv = ent + e0 * ES + G + jl;
+    const double *vBc = vB + c;
+    const double *zc = zblk + c;
+
+    // ping-pong: entry q in (xa, ba) while q+1 loads into (xb, bb), and so on;
+    // B slot indices two entries ahead, A slots are wave-uniform scalar loads.
+    double xa[G][NA], xb[G][NA], ba[B], bb[B];
+    int asa[G], asb[G];
+    int ia = entv[0], ib = entv[ES];
+    ia = (0 < n) ? ia : -1;
+    ib = (1 < n) ? ib : -1;
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        asa[a] = (0 < n) ? entu[a] : -1;
+        load_a<B, NA>(xa[a], vA, asa[a], l16);
+    }
+    load_b<B>(ba, vBc, zc, ia);
+    for (int q = 0; q < n; q += 2) {
+        int ic = entv[(int64_t)(q + 2) * ES];
+        ic = (q + 2 < n) ? ic : -1;
+#pragma unroll
+        for (int a = 0; a < G; ++a) {
+            asb[a] = entu[(int64_t)(q + 1) * ES + a];
+            load_a<B, NA>(xb[a], vA, asb[a], l16);
+        }
+        load_b<B>(bb, vBc, zc, ib);
+        dpp_entry<B, G, NA>(asa, xa, ba, acc);
+        int id = entv[(int64_t)(q + 3) * ES];
+        id = (q + 3 < n) ? id : -1;
+#pragma unroll
+        for (int a = 0; a < G; ++a) {
+            asa[a] = (q + 2 < n) ? entu[(int64_t)(q + 2) * ES + a] : -1;
+            load_a<B, NA>(xa[a], vA, asa[a], l16);
+        }
+        load_b<B>(ba, vBc, zc, ic);
+        dpp_entry<B, G, NA>(asb, xb, bb, acc);
+        ia = ic;
+        ib = id;
+    }
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (!cact[a]) continue;
+        double *cp = vC + (int64_t)cs[a] * BB + c;
+        if (beta == 0.0) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
         }
     }
-    // integer sums are exact, so the atomic order does not matter
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
-    if (lane == 0 && cnt) atomicAdd(total, (unsigned long long)cnt);
 }
 
-__global__ void k_tiles_per_row(int n, int jt, const int *__restrict__ rp, int *__restrict__ cnt)
+// ---------------------------------------------------------------- planner
+__device__ inline int find_in_row(const int *__restrict__ rp, const int *__restrict__ cols, int i, int j)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) cnt[i] = (rp[i + 1] - rp[i] + jt - 1) / jt;
+    int lo = rp[i], hi = rp[i + 1], end = hi;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (cols[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < end && cols[lo] == j) ? lo : -1;
 }
 
-__global__ void k_fill_tiles(int n, int jt, const int *__restrict__ rp, const int64_t *__restrict__ off,
-                             int2 *__restrict__ tiles)
+// One thread per row group: size of the union of the group's rows of P_C.
+__global__ void k_group_union(int n, int G, const int *__restrict__ rpC, const int *__restrict__ cC,
+                              int jt, int *__restrict__ ntile)
 {
-    int i = blockIdx.x;
-    if (i >= n) return;
-    int lo = rp[i], len = rp[i + 1] - lo;
-    int nt = (len + jt - 1) / jt;
-    for (int q = threadIdx.x; q < nt; q += blockDim.x) tiles[off[i] + q] = make_int2(i, lo + q * jt);
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ng = (n + G - 1) / G;
+    if (g >= ng) return;
+    int p[8], pe[8];
+    const int i0 = g * G, gr = min(G, n - i0);
+    for (int a = 0; a < gr; ++a) {
+        p[a] = rpC[i0 + a];
+        pe[a] = rpC[i0 + a + 1];
+    }
+    int cnt = 0;
+    while (true) {
+        int m = 0x7fffffff;
+        for (int a = 0; a < gr; ++a)
+            if (p[a] < pe[a]) m = min(m, cC[p[a]]);
+        if (m == 0x7fffffff) break;
+        for (int a = 0; a < gr; ++a)
+            if (p[a] < pe[a] && cC[p[a]] == m) ++p[a];
+        ++cnt;
+    }
+    ntile[g] = (cnt + jt - 1) / jt;
 }
 
-__global__ __launch_bounds__(1024) void k_scan64(int n, const int *__restrict__ in, int64_t *__restrict__ out)
+// One thread per row group: write the tile headers of its runs.
+__global__ void k_group_tiles(int n, int G, int jt, const int *__restrict__ rpC, const int *__restrict__ cC,
+                              const int64_t *__restrict__ toff, int *__restrict__ hdr, int *__restrict__ tcols)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ng = (n + G - 1) / G;
+    if (g >= ng) return;
+    const int hs = G + G * jt;
+    int p[8], pe[8];
+    const int i0 = g * G, gr = min(G, n - i0);
+    for (int a = 0; a < gr; ++a) {
+        p[a] = rpC[i0 + a];
+        pe[a] = rpC[i0 + a + 1];
+    }
+    int64_t t = toff[g];
+    int q = 0;
+    int *h = nullptr;
+    while (true) {
+        int m = 0x7fffffff;
+        for (int a = 0; a < gr; ++a)
+            if (p[a] < pe[a]) m = min(m, cC[p[a]]);
+        if (m == 0x7fffffff) break;
+        if (q == 0) {
+            h = hdr + t * hs;
+            for (int a = 0; a < G; ++a) h[a] = (a < gr) ? i0 + a : -1;
+            for (int x = 0; x < G * jt; ++x) h[G + x] = -1;
+            for (int x = 0; x < jt; ++x) tcols[t * jt + x] = -1;
+        }
+        tcols[t * jt + q] = m;
+        for (int a = 0; a < gr; ++a)
+            if (p[a] < pe[a] && cC[p[a]] == m) {
+                h[G + a * jt + q] = p[a];
+                ++p[a];
+            }
+        if (++q == jt) {
+            q = 0;
+            ++t;
+        }
+    }
+}
+
+// One thread per tile: walk the union over the group's rows of P_A (k ascending);
+// keep k when some (i_a, k, j) triple exists.  MODE 0 counts entries and triples,
+// MODE 1 writes the entries.
+template <int MODE>
+__global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restrict__ hdr,
+                               const int *__restrict__ tcols, const int *__restrict__ rpA,
+                               const int *__restrict__ cA, const int *__restrict__ rpB,
+                               const int *__restrict__ cB, const int *__restrict__ tmB,
+                               int64_t *__restrict__ nent, unsigned long long *__restrict__ triples,
+                               const int64_t *__restrict__ ebeg, int *__restrict__ ent)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int hs = G + G * jt, es = G + jt;
+    const int *h = hdr + t * hs;
+    int pa[8], pae[8], pb[64], pbe[64], jcol[64];
+    bool crow[8][64];
+    for (int a = 0; a < G; ++a) {
+        const int i = h[a];
+        pa[a] = (i >= 0) ? rpA[i] : 0;
+        pae[a] = (i >= 0) ? rpA[i + 1] : 0;
+        for (int x = 0; x < jt; ++x) crow[a][x] = h[G + a * jt + x] >= 0;
+    }
+    for (int x = 0; x < jt; ++x) {
+        const int j = tcols[t * jt + x];
+        jcol[x] = j;
+        pb[x] = (j >= 0) ? rpB[j] : 0;
+        pbe[x] = (j >= 0) ? rpB[j + 1] : 0;
+    }
+    int64_t w = (MODE == 1) ? ebeg[t] : 0;
+    int64_t cnt = 0;
+    unsigned long long tri = 0;
+    while (true) {
+        int k = 0x7fffffff;
+        for (int a = 0; a < G; ++a)
+            if (pa[a] < pae[a]) k = min(k, cA[pa[a]]);
+        if (k == 0x7fffffff) break;
+        int aslot[8];
+        for (int a = 0; a < G; ++a) {
+            aslot[a] = -1;
+            if (pa[a] < pae[a] && cA[pa[a]] == k) aslot[a] = pa[a]++;
+        }
+        int bslot[64];
+        int ntri = 0;
+        for (int x = 0; x < jt; ++x) {
+            bslot[x] = -1;
+            if (jcol[x] < 0) continue;
+            while (pb[x] < pbe[x] && cB[pb[x]] < k) ++pb[x];
+            if (pb[x] < pbe[x] && cB[pb[x]] == k) bslot[x] = tmB[pb[x]];   // slot of (k, j)
+            if (bslot[x] < 0) continue;
+            for (int a = 0; a < G; ++a) ntri += (aslot[a] >= 0 && crow[a][x]) ? 1 : 0;
+        }
+        if (ntri == 0) continue;
+        if (MODE == 1) {
+            int *e = ent + w * es;
+            for (int a = 0; a < G; ++a) e[a] = aslot[a];
+            for (int x = 0; x < jt; ++x) e[G + x] = bslot[x];
+        }
+        ++w;
+        ++cnt;
+        tri += ntri;
+    }
+    if (cnt & 1) {   // pad to an even count with an entry that multiplies nothing
+        if (MODE == 1) {
+            int *e = ent + w * es;
+            for (int a = 0; a < G; ++a) e[a] = -1;
+            for (int x = 0; x < jt; ++x) e[G + x] = -1;
+        }
+        ++cnt;
+    }
+    if (MODE == 0) {
+        nent[t] = cnt;
+        atomicAdd(triples, tri);   // integer: order-independent
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan64(int64_t n, const int64_t *__restrict__ in, int64_t *__restrict__ out)
 {
     __shared__ long long part[1024];
     const int t = threadIdx.x, nt = blockDim.x;
-    const int chunk = (n + nt - 1) / nt;
-    const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+    const int64_t chunk = (n + nt - 1) / nt;
+    const int64_t lo = min(n, (int64_t)t * chunk), hi = min(n, lo + chunk);
     long long s = 0;
-    for (int k = lo; k < hi; ++k) s += in[k];
+    for (int64_t k = lo; k < hi; ++k) s += in[k];
     part[t] = s;
     __syncthreads();
     for (int off = 1; off < nt; off <<= 1) {
@@ -160,35 +519,60 @@ __global__ __launch_bounds__(1024) void k_scan64(int n, const int *__restrict__ 
         __syncthreads();
     }
     long long run = part[t] - s;
-    for (int k = lo; k < hi; ++k) {
+    for (int64_t k = lo; k < hi; ++k) {
         out[k] = run;
         run += in[k];
     }
     if (t == nt - 1) out[n] = part[t];
 }
 
-int jt_for(int b) { return 64 / b; }
-
-template <int B>
-void launch_b(hipStream_t st, const Plan *plan, double alpha, const bsm_pattern_s *PA, const double *A,
-              const bsm_pattern_s *PB, const double *Bm, double beta, const bsm_pattern_s *PC, double *C)
+__global__ void k_int_to_i64(int n, const int *__restrict__ in, int64_t *__restrict__ out)
 {
-    const int64_t waves = plan->ntiles;
-    const unsigned grid = (unsigned)((waves + 3) / 4);
-    k_product_f64<B><<<grid, 256, 0, st>>>(
-        plan->tiles.as<int2>(), waves, PA->rowptr.as<int>(), PA->cols.as<int>(), A,
-        PB->rowptr.as<int>(), PB->cols.as<int>(), PB->tmap.as<int>(), Bm,
-        PC->rowptr.as<int>(), PC->cols.as<int>(), C, alpha, beta);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+template <int B, int G>
+void launch_bg(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
+               double beta)
+{
+    const int64_t nwg = (plan->ntiles + kWaves - 1) / kWaves;
+    const int64_t nwg_padded = ((nwg + kXcd - 1) / kXcd) * kXcd;
+    k_product_f64<B, G><<<(unsigned)nwg_padded, 64 * kWaves, 0, st>>>(
+        plan->ntiles, nwg_padded, plan->hdr.as<int>(), plan->ebeg.as<int64_t>(), plan->ent.as<int>(), A, Bm, C,
+        alpha, beta);
+}
+
+template <int B, int G>
+void launch_dpp(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
+                double beta, const double *zblk)
+{
+    const int64_t nwg = (plan->ntiles + kWaves - 1) / kWaves;
+    const int64_t nwg_padded = ((nwg + kXcd - 1) / kXcd) * kXcd;
+    k_product_f64_dpp<B, G><<<(unsigned)nwg_padded, 64 * kWaves, 0, st>>>(
+        plan->ntiles, nwg_padded, plan->hdr.as<int>(), plan->ebeg.as<int64_t>(), plan->ent.as<int>(), A, Bm,
+        zblk, C, alpha, beta);
 }
 
 template <int B>
-void count_b(hipStream_t st, const Plan *plan, const bsm_pattern_s *PA, const bsm_pattern_s *PB,
-             const bsm_pattern_s *PC, unsigned long long *total)
+void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
+              double beta, const double *zblk)
 {
-    const unsigned grid = (unsigned)((plan->ntiles + 3) / 4);
-    k_count_triples<B><<<grid, 256, 0, st>>>(plan->tiles.as<int2>(), plan->ntiles, PA->rowptr.as<int>(),
-                                             PA->cols.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
-                                             PC->rowptr.as<int>(), PC->cols.as<int>(), total);
+    if constexpr (B == 9 || B == 4) {
+        if (plan->variant == 1) {
+            switch (plan->G) {
+                case 2: launch_dpp<B, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                case 4: launch_dpp<B, 4>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                default: break;
+            }
+        }
+    }
+    switch (plan->G) {
+        case 2: launch_bg<B, 2>(st, plan, A, Bm, C, alpha, beta); break;
+        case 4: launch_bg<B, 4>(st, plan, A, Bm, C, alpha, beta); break;
+        case 8: launch_bg<B, 8>(st, plan, A, Bm, C, alpha, beta); break;
+        default: throw Error{BSM_EINVAL, "rows per wave must be 2, 4 or 8"};
+    }
 }
 
 #define BSM_FOR_EACH_B(X) \
@@ -196,49 +580,70 @@ void count_b(hipStream_t st, const Plan *plan, const bsm_pattern_s *PA, const bs
 
 }  // namespace
 
-void build_tiles(Context *ctx, const bsm_pattern_s *PC, Plan *plan)
-{
-    hipStream_t st = ctx->stream;
-    const int n = PC->natoms;
-    plan->jt = jt_for(PC->b);
-    DevBuf cnt(ctx, sizeof(int) * n), off(ctx, sizeof(int64_t) * (n + 1));
-    k_tiles_per_row<<<(n + 255) / 256, 256, 0, st>>>(n, plan->jt, PC->rowptr.as<int>(), cnt.as<int>());
-    k_scan64<<<1, 1024, 0, st>>>(n, cnt.as<int>(), off.as<int64_t>());
-    int64_t total = 0;
-    BSM_HIP_TRY(hipMemcpyAsync(&total, off.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    BSM_HIP_TRY(hipStreamSynchronize(st));
-    plan->ntiles = total;
-    plan->tiles = DevBuf(ctx, sizeof(int2) * (size_t)std::max<int64_t>(total, 1));
-    k_fill_tiles<<<n, 64, 0, st>>>(n, plan->jt, PC->rowptr.as<int>(), off.as<int64_t>(),
-                                   plan->tiles.as<int2>());
-    BSM_HIP_TRY(hipGetLastError());
-}
+int default_rows_per_wave(int b) { return b >= 9 ? 4 : (b >= 5 ? 4 : 2); }
 
-int64_t count_triples(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB,
-                      const bsm_pattern_s *PC, const Plan *plan)
+void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
+                Plan *plan, int G)
 {
     hipStream_t st = ctx->stream;
-    DevBuf total(ctx, sizeof(unsigned long long));
-    BSM_HIP_TRY(hipMemsetAsync(total.ptr, 0, sizeof(unsigned long long), st));
-    if (plan->ntiles > 0) {
-        switch (PC->b) {
-#define X(b) \
-    case b: count_b<b>(st, plan, PA, PB, PC, total.as<unsigned long long>()); break;
-            BSM_FOR_EACH_B(X)
-#undef X
-            default: throw Error{BSM_EINVAL, "b must be in 1..16"};
-        }
-    }
-    unsigned long long h = 0;
-    BSM_HIP_TRY(hipMemcpyAsync(&h, total.ptr, sizeof(h), hipMemcpyDeviceToHost, st));
+    const int n = PC->natoms, jt = 64 / PC->b;
+    BSM_REQUIRE(G == 2 || G == 4 || G == 8, BSM_EINVAL, "rows per wave must be 2, 4 or 8");
+    plan->G = G;
+    plan->jt = jt;
+    const int ng = (n + G - 1) / G;
+    const int hs = G + G * jt, es = G + jt;
+    DevBuf ntile(ctx, sizeof(int) * ng), ntile64(ctx, sizeof(int64_t) * ng), toff(ctx, sizeof(int64_t) * (ng + 1));
+    k_group_union<<<(ng + 127) / 128, 128, 0, st>>>(n, G, PC->rowptr.as<int>(), PC->cols.as<int>(), jt,
+                                                    ntile.as<int>());
+    k_int_to_i64<<<(ng + 255) / 256, 256, 0, st>>>(ng, ntile.as<int>(), ntile64.as<int64_t>());
+    k_scan64<<<1, 1024, 0, st>>>(ng, ntile64.as<int64_t>(), toff.as<int64_t>());
+    int64_t nt = 0;
+    BSM_HIP_TRY(hipMemcpyAsync(&nt, toff.as<int64_t>() + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     BSM_HIP_TRY(hipStreamSynchronize(st));
-    return (int64_t)h;
+    plan->ntiles = nt;
+    plan->hdr = DevBuf(ctx, sizeof(int) * (size_t)std::max<int64_t>(1, nt * hs));
+    DevBuf tcols(ctx, sizeof(int) * (size_t)std::max<int64_t>(1, nt * jt));
+    k_group_tiles<<<(ng + 127) / 128, 128, 0, st>>>(n, G, jt, PC->rowptr.as<int>(), PC->cols.as<int>(),
+                                                    toff.as<int64_t>(), plan->hdr.as<int>(), tcols.as<int>());
+    DevBuf nent(ctx, sizeof(int64_t) * (size_t)std::max<int64_t>(1, nt)), tri(ctx, sizeof(unsigned long long));
+    plan->ebeg = DevBuf(ctx, sizeof(int64_t) * (size_t)(nt + 1));
+    BSM_HIP_TRY(hipMemsetAsync(tri.ptr, 0, sizeof(unsigned long long), st));
+    BSM_HIP_TRY(hipMemsetAsync(plan->ebeg.ptr, 0, sizeof(int64_t) * (size_t)(nt + 1), st));
+    int64_t ne = 0;
+    unsigned long long ntri = 0;
+    if (nt > 0) {
+        const unsigned grid = (unsigned)((nt + 127) / 128);
+        k_tile_entries<0><<<grid, 128, 0, st>>>(nt, G, jt, plan->hdr.as<int>(), tcols.as<int>(), PA->rowptr.as<int>(),
+                                                PA->cols.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
+                                                PB->tmap.as<int>(), nent.as<int64_t>(),
+                                                tri.as<unsigned long long>(), nullptr, nullptr);
+        k_scan64<<<1, 1024, 0, st>>>(nt, nent.as<int64_t>(), plan->ebeg.as<int64_t>());
+        BSM_HIP_TRY(hipMemcpyAsync(&ne, plan->ebeg.as<int64_t>() + nt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        BSM_HIP_TRY(hipMemcpyAsync(&ntri, tri.ptr, sizeof(ntri), hipMemcpyDeviceToHost, st));
+        BSM_HIP_TRY(hipStreamSynchronize(st));
+        plan->ent = DevBuf(ctx, sizeof(int) * (size_t)((ne + 4) * es));   // 4 spare entries
+        BSM_HIP_TRY(hipMemsetAsync(plan->ent.as<int>() + ne * es, 0xff, sizeof(int) * 4 * es, st));
+        k_tile_entries<1><<<grid, 128, 0, st>>>(nt, G, jt, plan->hdr.as<int>(), tcols.as<int>(), PA->rowptr.as<int>(),
+                                                PA->cols.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
+                                                PB->tmap.as<int>(), nullptr, nullptr, plan->ebeg.as<int64_t>(),
+                                                plan->ent.as<int>());
+        BSM_HIP_TRY(hipGetLastError());
+    } else {
+        plan->ent = DevBuf(ctx, sizeof(int) * 4 * es);
+        BSM_HIP_TRY(hipMemsetAsync(plan->ent.ptr, 0xff, sizeof(int) * 4 * es, st));
+    }
+    BSM_HIP_TRY(hipStreamSynchronize(st));
+    plan->nentries = ne;
+    plan->triples = (int64_t)ntri;
+    plan->flops = 2.0 * (double)PC->b * PC->b * PC->b * (double)ntri;
 }
 
 void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
                         const double *A, const bsm_pattern_s *PB, const double *Bm, double beta,
                         const bsm_pattern_s *PC, double *C)
 {
+    (void)PA;
+    (void)PB;
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
     Context::ProfRec rec{plan, nullptr, nullptr};
@@ -249,7 +654,7 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
     }
     switch (PC->b) {
 #define X(b) \
-    case b: launch_b<b>(st, plan, alpha, PA, A, PB, Bm, beta, PC, C); break;
+    case b: launch_b<b>(st, plan, A, Bm, C, alpha, beta, ctx->zero_block.as<double>()); break;
         BSM_FOR_EACH_B(X)
 #undef X
         default: throw Error{BSM_EINVAL, "b must be in 1..16"};
@@ -275,9 +680,9 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
     plan->cutoffs[2] = C->cutoff;
     plan->natoms = C->natoms;
     plan->b = C->b;
-    build_tiles(ctx, C, plan.get());
-    plan->triples = count_triples(ctx, A, B, C, plan.get());
-    plan->flops = 2.0 * (double)C->b * C->b * C->b * (double)plan->triples;
+    const int G = ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b);
+    build_plan(ctx, A, B, C, plan.get(), G);
+    plan->variant = ctx->product_variant;
     Plan *raw = plan.get();
     ctx->plans[key] = std::move(plan);
     return raw;

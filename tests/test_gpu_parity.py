@@ -128,6 +128,29 @@ def test_product_parity(bsm, ctx, b):
         assert bsm.product_flops(gp[ra], gp[rb], gp[rc]) == 2.0 * b ** 3 * tri
 
 
+@pytest.mark.parametrize("variant,rows", [(0, 2), (0, 4), (0, 8), (1, 2), (1, 4)])
+@pytest.mark.parametrize("b", [4, 9])
+def test_product_kernel_variants(bsm, b, variant, rows):
+    """Every product kernel variant and rows-per-wave choice gives the oracle's result."""
+    ctx = bsm.Context(0)
+    ctx.set_product_variant(variant)
+    ctx.set_rows_per_wave(rows)
+    s = SYSTEMS["si256_disp"]()
+    say(f"product variant={variant} rows={rows} b={b}")
+    gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
+    for n, (ra, rb, rc) in enumerate([(6, 8, 14), (14, 8, 6), (8, 8, 8)]):
+        a = synth.random_blocks(op[ra].nnz, b, 40 + n)
+        bb = synth.random_blocks(op[rb].nnz, b, 50 + n)
+        c0 = synth.random_blocks(op[rc].nnz, b, 60 + n)
+        A, B, C = gmat(bsm, gp[ra], a), gmat(bsm, gp[rb], bb), gmat(bsm, gp[rc], c0)
+        bsm.multiply_truncate(1.25, A, B, 0.5, C)
+        Co = O.Matrix(op[rc], b, c0.copy())
+        O.multiply_truncate(1.25, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), 0.5, Co)
+        assert rel_err(host(C), Co.blocks) < 1e-12, (ra, rb, rc)
+    ctx.close()
+
+
 def test_product_beta_zero_ignores_nan_and_is_deterministic(bsm, ctx):
     s = SYSTEMS["si64"]()
     P6, P8 = (gpat(bsm, ctx, s.positions, s.box, r, 4) for r in (6.0, 8.0))
