@@ -121,10 +121,16 @@ typedef struct {
 int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
 /* FP64 product kernel of plans built from now on: 0 = the uniform A block read
  * through the scalar cache into SGPRs; 1 = A held in VGPRs and broadcast by DPP
- * (b = 4 and 9, rows per wave 2 or 4; other shapes use 0).  Variant 1 multiplies
+ * (b = 4 and 9, rows per wave 2 or 4; other shapes use 0); -1 = default (1 for
+ * b = 4 and 9, else 0).  Variant 1 multiplies
  * absent (k, j) blocks by zero instead of skipping them, so a non-finite block
  * of A can make other blocks of its output row non-finite.  Clears cached plans. */
 int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant);
+/* Launch order of product tiles in plans built from now on: tiles of `span`
+ * consecutive row groups are interleaved by column position (1 = group by
+ * group), so that groups over similar columns share B blocks in L2.
+ * 1 <= span <= 4096 (default 4).  Clears cached plans. */
+int bsm_ctx_set_group_span(bsm_ctx ctx, int span);
 
 /* enable != 0 clears the statistics and starts recording; 0 stops. */
 int bsm_ctx_set_profiling(bsm_ctx ctx, int enable);

@@ -225,11 +225,24 @@ int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant)
 {
     BSM_API_BEGIN
     BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
-    BSM_REQUIRE(variant == 0 || variant == 1, BSM_EINVAL, "variant must be 0 or 1");
+    BSM_REQUIRE(variant >= -1 && variant <= 1, BSM_EINVAL, "variant must be -1, 0 or 1");
     BSM_HIP_TRY(hipStreamSynchronize(ctx->c.stream));
     ctx->c.retire_profile([](const Plan *) { return true; });
     ctx->c.plans.clear();
     ctx->c.product_variant = variant;
+    return BSM_OK;
+    BSM_API_END
+}
+
+int bsm_ctx_set_group_span(bsm_ctx ctx, int span)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
+    BSM_REQUIRE(span >= 1 && span <= 4096, BSM_EINVAL, "span must be in 1..4096");
+    BSM_HIP_TRY(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.retire_profile([](const Plan *) { return true; });
+    ctx->c.plans.clear();
+    ctx->c.group_span = span;
     return BSM_OK;
     BSM_API_END
 }

@@ -65,6 +65,8 @@ struct Plan {
     int jt = 0;                 // output block columns per wavefront tile (64 / b)
     int64_t ntiles = 0;
     int64_t nentries = 0;
+    int span = 1;               // row groups interleaved in the launch order
+    DevBuf order;               // int [ntiles]: launch slot -> tile
     DevBuf hdr;                 // int [ntiles][G + G*jt]: rows, C slots
     DevBuf ebeg;                // int64 [ntiles + 1]: entry ranges
     DevBuf ent;                 // int [nentries][G + jt]: A slots, B slots
@@ -81,7 +83,8 @@ class Context {
     void *user = nullptr;
     uint64_t next_pattern_id = 1;
     int rows_per_wave = 0;      // product plans: 0 = per-b default, else 2, 4 or 8
-    int product_variant = 0;    // product kernel variant of plans built from now on
+    int product_variant = -1;   // product kernel variant of plans built from now on (-1: per-b default)
+    int group_span = 4;         // row groups interleaved in product launch order
     // derived patterns (same atoms, another cutoff), owned here, keyed by (source id, cutoff)
     std::map<std::pair<uint64_t, double>, bsm_pattern_s *> derived;
     std::map<std::tuple<uint64_t, uint64_t, uint64_t>, std::unique_ptr<Plan>> plans;

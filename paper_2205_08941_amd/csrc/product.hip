@@ -25,7 +25,9 @@
 #include "bsm_internal.h"
 
 #include <algorithm>
+#include <climits>
 #include <utility>
+#include <vector>
 
 namespace bsm {
 namespace {
@@ -75,16 +77,17 @@ __device__ inline void multiply_entry(const_as4<int> *entu, int64_t q, const_as4
 // prefetch past a tile's last entry stays in bounds.
 template <int B, int G>
 __global__ __launch_bounds__(256) void k_product_f64(
-    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
-    const int *__restrict__ ent, const double *__restrict__ vA, const double *__restrict__ vB,
-    double *__restrict__ vC, double alpha, double beta)
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
+    const double *__restrict__ vB, double *__restrict__ vC, double alpha, double beta)
 {
     constexpr int JT = 64 / B;
     constexpr int BB = B * B;
     constexpr int HS = G + G * JT;
     constexpr int ES = G + JT;
-    const int64_t tile = logical_workgroup(nwg_padded) * kWaves + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;
+    const int64_t slot = logical_workgroup(nwg_padded) * kWaves + (threadIdx.x >> 6);
+    if (slot >= ntiles) return;
+    const int64_t tile = order[slot];
     const int lane = threadIdx.x & 63;
     const int jl0 = lane / B, c = lane - jl0 * B;
     const bool lane_ok = jl0 < JT;
@@ -258,17 +261,19 @@ __device__ inline void dpp_entry(const int (&as)[G], const double (&av)[G][NA], 
 
 template <int B, int G>
 __global__ __launch_bounds__(256) void k_product_f64_dpp(
-    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
-    const int *__restrict__ ent, const double *__restrict__ vA, const double *__restrict__ vB,
-    const double *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta)
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
+    const double *__restrict__ vB, const double *__restrict__ zblk, double *__restrict__ vC, double alpha,
+    double beta)
 {
     constexpr int JT = 64 / B;
     constexpr int BB = B * B;
     constexpr int NA = (BB + 15) / 16;
     constexpr int HS = G + G * JT;
     constexpr int ES = G + JT;
-    const int64_t tile = logical_workgroup(nwg_padded) * kWaves + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;
+    const int64_t slot = logical_workgroup(nwg_padded) * kWaves + (threadIdx.x >> 6);
+    if (slot >= ntiles) return;
+    const int64_t tile = order[slot];
     const int lane = threadIdx.x & 63;
     const int l16 = lane & 15;
     const int jl0 = lane / B, c = lane - jl0 * B;
@@ -539,8 +544,8 @@ void launch_bg(hipStream_t st, const Plan *plan, const double *A, const double *
     const int64_t nwg = (plan->ntiles + kWaves - 1) / kWaves;
     const int64_t nwg_padded = ((nwg + kXcd - 1) / kXcd) * kXcd;
     k_product_f64<B, G><<<(unsigned)nwg_padded, 64 * kWaves, 0, st>>>(
-        plan->ntiles, nwg_padded, plan->hdr.as<int>(), plan->ebeg.as<int64_t>(), plan->ent.as<int>(), A, Bm, C,
-        alpha, beta);
+        plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+        plan->ent.as<int>(), A, Bm, C, alpha, beta);
 }
 
 template <int B, int G>
@@ -550,8 +555,8 @@ void launch_dpp(hipStream_t st, const Plan *plan, const double *A, const double 
     const int64_t nwg = (plan->ntiles + kWaves - 1) / kWaves;
     const int64_t nwg_padded = ((nwg + kXcd - 1) / kXcd) * kXcd;
     k_product_f64_dpp<B, G><<<(unsigned)nwg_padded, 64 * kWaves, 0, st>>>(
-        plan->ntiles, nwg_padded, plan->hdr.as<int>(), plan->ebeg.as<int64_t>(), plan->ent.as<int>(), A, Bm,
-        zblk, C, alpha, beta);
+        plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+        plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta);
 }
 
 template <int B>
@@ -580,7 +585,8 @@ void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *B
 
 }  // namespace
 
-int default_rows_per_wave(int b) { return b >= 9 ? 4 : (b >= 5 ? 4 : 2); }
+int default_rows_per_wave(int b) { return b >= 5 ? 4 : (b == 4 ? 4 : 2); }
+int default_variant(int b) { return (b == 9 || b == 4) ? 1 : 0; }
 
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
                 Plan *plan, int G)
@@ -601,6 +607,33 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
     BSM_HIP_TRY(hipMemcpyAsync(&nt, toff.as<int64_t>() + ng, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     BSM_HIP_TRY(hipStreamSynchronize(st));
     plan->ntiles = nt;
+    BSM_REQUIRE(nt < (int64_t)INT32_MAX, BSM_EINVAL, "too many product tiles");
+    {
+        // launch order: within each span of `span` consecutive row groups, chunk
+        // position first, so that the groups' tiles over similar columns run
+        // together and share B blocks in L2
+        std::vector<int> cnt(ng);
+        std::vector<int64_t> off(ng + 1);
+        BSM_HIP_TRY(hipMemcpyAsync(cnt.data(), ntile.ptr, sizeof(int) * ng, hipMemcpyDeviceToHost, st));
+        BSM_HIP_TRY(hipMemcpyAsync(off.data(), toff.ptr, sizeof(int64_t) * (ng + 1), hipMemcpyDeviceToHost, st));
+        BSM_HIP_TRY(hipStreamSynchronize(st));
+        std::vector<int> order;
+        order.reserve((size_t)nt);
+        const int span = std::max(1, ctx->group_span);
+        for (int g0 = 0; g0 < ng; g0 += span) {
+            const int g1 = std::min(ng, g0 + span);
+            int qmax = 0;
+            for (int g = g0; g < g1; ++g) qmax = std::max(qmax, cnt[g]);
+            for (int q = 0; q < qmax; ++q)
+                for (int g = g0; g < g1; ++g)
+                    if (q < cnt[g]) order.push_back((int)(off[g] + q));
+        }
+        plan->order = DevBuf(ctx, sizeof(int) * (size_t)std::max<int64_t>(1, nt));
+        if (nt > 0)
+            BSM_HIP_TRY(hipMemcpyAsync(plan->order.ptr, order.data(), sizeof(int) * (size_t)nt, hipMemcpyHostToDevice, st));
+        BSM_HIP_TRY(hipStreamSynchronize(st));
+        plan->span = span;
+    }
     plan->hdr = DevBuf(ctx, sizeof(int) * (size_t)std::max<int64_t>(1, nt * hs));
     DevBuf tcols(ctx, sizeof(int) * (size_t)std::max<int64_t>(1, nt * jt));
     k_group_tiles<<<(ng + 127) / 128, 128, 0, st>>>(n, G, jt, PC->rowptr.as<int>(), PC->cols.as<int>(),
@@ -682,7 +715,7 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
     plan->b = C->b;
     const int G = ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b);
     build_plan(ctx, A, B, C, plan.get(), G);
-    plan->variant = ctx->product_variant;
+    plan->variant = ctx->product_variant >= 0 ? ctx->product_variant : default_variant(C->b);
     Plan *raw = plan.get();
     ctx->plans[key] = std::move(plan);
     return raw;
