@@ -45,7 +45,43 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=1024,
                     help="rows of the 16 A x 16 A product the oracle computes for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="solve", choices=["solve", "product"],
+                    help="product: only the dominant 16 A x 16 A -> 16 A product, --steps launches, plus a "
+                         "2 GiB device copy (for hardware-counter runs and their byte calibration)")
     return ap.parse_args()
+
+
+def product_mode(args):
+    """The dominant product class alone, in the launch the solve uses, for counter runs."""
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    n, b = (8, 9) if args.workload == "si4096_b9" else (2, 4)
+    s = synth.si4096_b9() if args.workload == "si4096_b9" else synth.si64_b4()
+    rx = s.cutoffs["L"] + s.cutoffs["S"]
+    ctx = bsm.Context(0)
+    pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
+    P = bsm.Pattern(ctx, pos, s.box, rx, b)
+    g = torch.Generator(device=ctx.device)
+    g.manual_seed(7)
+    X = bsm.Matrix(P, torch.rand((P.nnzb, b, b), dtype=torch.float64, device=ctx.device, generator=g) - 0.5)
+    C = bsm.Matrix(P)
+    flops = bsm.product_flops(P, P, P)
+    ctx.set_profiling(True)
+    for k in range(args.steps):
+        bsm.multiply_truncate(1.0, X, X, 0.0, C)
+        torch.cuda.synchronize()
+        log(f"[product] launch {k}")
+    st = ctx.product_stats()[0]
+    src = torch.empty(1 << 28, dtype=torch.float64, device=ctx.device).fill_(1.0)   # 2 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = st["ms"] / st["launches"]
+    print(json.dumps({"mode": "product", "flops_per_launch": flops, "avg_ms": ms,
+                      "tflops": flops / (ms * 1e-3) / 1e12, "blocks": P.nnzb,
+                      "algorithmic_bytes": 3 * P.nnzb * b * b * 8, "copy_bytes": 2 * src.numel() * 8}),
+          flush=True)
 
 
 def cpu_baseline(args):
@@ -61,18 +97,32 @@ def cpu_baseline(args):
     rng = np.random.default_rng(7)
     X = O.Matrix(P, b, rng.uniform(-1, 1, (P.nnz, b, b)))
     C = O.Matrix(P, b)
-    rows = np.linspace(0, P.natoms - 1, min(args.cpu_rows, P.natoms)).astype(int)
+    nrows = min(args.cpu_rows, P.natoms)
     tri = O.count_triples(P, P, P)
-    flops = 2.0 * b ** 3 * float(tri[rows].sum())
+    flops = 2.0 * b ** 3 * float(tri[:nrows].sum())
     cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
     t0 = time.perf_counter()
-    for r in rows:
-        O.multiply_truncate(1.0, X, X, 0.0, C, int(r), int(r) + 1)
+    O.multiply_truncate(1.0, X, X, 0.0, C, 0, nrows)     # OpenMP over the rows
     dt = time.perf_counter() - t0
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(rows)} of {P.natoms} output block-rows of the {rx:g} A x {rx:g} A -> {rx:g} A "
+            "sample": f"output block-rows 0..{nrows - 1} of {P.natoms} of the {rx:g} A x {rx:g} A -> {rx:g} A "
                       f"product (the class holding ~90% of LNV flops), random FP64 blocks, "
                       f"{flops / 1e9:.1f} GFLOP in {dt:.1f} s"}
+
+
+def measured_traffic(kernel_src: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_product_f64_dpp_si4096_b9_traffic.json")
+    try:
+        d = json.load(open(path))
+        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()[:16]
+        if d.get("source_sha256_16") != sha:
+            return None
+        return d["hbm_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -89,6 +139,9 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
+    if args.mode == "product":
+        product_mode(args)
+        return
     s = synth.si4096_b9() if args.workload == "si4096_b9" else synth.si64_b4()
     cut = s.cutoffs
     ctx = bsm.Context(0)
@@ -186,7 +239,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic("paper_2205_08941_amd/csrc/product.hip") if s.b == 9 else None,
             "avg_launch_ms": round(avg_ms, 3),
             "launches": top["launches"],
             "flops_per_launch": per_launch_flops,
