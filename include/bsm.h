@@ -185,6 +185,16 @@ int bsm_dot(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, double *out);
  * blocks alias A's or B's, dtype not F64), BSM_ENOMEM, BSM_EHIP. */
 int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *B,
                           double beta, const bsm_matrix *C);
+/* The same product with every element of A and B first rounded to `precision`:
+ * BSM_F32 (round to nearest even) or BSM_BF16 (to FP32, then to 8 significant
+ * bits, nearest even); products accumulated in FP32 by fused multiply-adds over
+ * k ascending, then the block's inner index ascending; the FP32 sum is widened
+ * exactly to FP64 and C <- alpha sum + beta C in FP64.  BSM_F64 is
+ * bsm_multiply_truncate.  A and B stay FP64 in memory; their rounded copies live
+ * in context scratch.  Used for the low-precision stages of an LNV solve with
+ * FP64 traces and refinement (spec extension, not in the paper). */
+int bsm_multiply_truncate_prec(bsm_ctx ctx, int precision, double alpha, const bsm_matrix *A,
+                               const bsm_matrix *B, double beta, const bsm_matrix *C);
 /* Algorithmic flops of mask_{P_C}(A B): 2 b^3 per block triple (i, k, j). */
 int bsm_product_flops(bsm_ctx ctx, bsm_pattern PA, bsm_pattern PB, bsm_pattern PC, double *flops);
 
@@ -236,6 +246,8 @@ typedef struct {
     double mu;           /* fixed chemical potential for LNV_GRAND */
     double tol_E;        /* converged when |E_n - E_(n-1)| < tol_E (Ha) */
     int init_from_z;     /* 1: L <- c mask_L(Z) with N(c Z) = N_e; 0: use L as given */
+    int product_precision; /* BSM_F64 (default 0), BSM_F32 or BSM_BF16 for every product
+                              of a step (bsm_multiply_truncate_prec); traces stay FP64 */
 } lnv_params;
 
 typedef struct {
@@ -272,6 +284,39 @@ int lnv_step(lnv_state *st, lnv_result *result);
  * the two products that takes.  Patterns and product plans are kept. */
 int lnv_state_reset(lnv_state *st, const lnv_params *params, double *init_flops);
 int lnv_state_destroy(lnv_state *st);
+
+/* Idempotency diagnostic of the current L: with KS = 3 W - 2 mask_X(W X) on
+ * P_X = P(r_L + r_S) (W = X X, X = L S; the truncated form of K S for
+ * K = 3LSL - 2LSLSL), *e_idem = ||mask_X(KS KS) - KS||_F / ||KS||_F, which
+ * vanishes when K S K = K.  FP64 products; overwrites the state's P_X scratch
+ * (harmless: every step recomputes it).  Synchronises. */
+int lnv_idempotency_error(lnv_state *st, double *e_idem);
+
+/* A precision schedule for a whole solve (spec extension: low-precision
+ * products with FP64 traces, then FP64 refinement).  Stage s runs lnv_step with
+ * products in precision[s] until |dE| < tol_E[s] (tol_E[s] > 0), or, when
+ * stop_on_rise[s], until E fails to decrease (the rounding floor of that
+ * precision), or max_iter[s] steps.  The first stage continues the state as
+ * created or reset; each later stage keeps L and restarts the conjugate
+ * gradients.  A last stage with tol_E = 0 runs exactly max_iter FP64 steps. */
+#define LNV_MAX_STAGES 4
+typedef struct {
+    int n_stages;
+    int precision[LNV_MAX_STAGES];
+    int max_iter[LNV_MAX_STAGES];
+    double tol_E[LNV_MAX_STAGES];
+    int stop_on_rise[LNV_MAX_STAGES];
+} lnv_schedule;
+
+typedef struct {
+    int status;                      /* BSM_OK or the failing step's status */
+    int converged;                   /* last stage met its stop rule (tol or count) */
+    int iterations[LNV_MAX_STAGES];  /* steps taken per stage */
+    double E, N, mu;                 /* last step's values (at the L it started from) */
+    double product_flops;            /* algorithmic flops of all products */
+} lnv_solve_result;
+
+int lnv_solve(lnv_state *st, const lnv_schedule *schedule, lnv_solve_result *result);
 
 #ifdef __cplusplus
 }

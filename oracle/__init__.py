@@ -73,6 +73,11 @@ def _lib():
                                    ctypes.c_double, P, P, P, ctypes.c_int, ctypes.c_int]
         L.orc_count_triples.restype = None
         L.orc_count_triples.argtypes = [ctypes.c_int, P, P, P, P, P, P, P]
+        L.orc_multiply_mixed.restype = None
+        L.orc_multiply_mixed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, P, P, P, P,
+                                         P, P, ctypes.c_double, P, P, P, ctypes.c_int, ctypes.c_int]
+        L.orc_round_bf16.restype = ctypes.c_float
+        L.orc_round_bf16.argtypes = [ctypes.c_float]
         L.orc_trace_product.restype = ctypes.c_double
         L.orc_trace_product.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
         _lib_handle = L
@@ -221,9 +226,35 @@ def multiply_truncate(alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix
                         int(row_begin), int(row_end))
 
 
-def product(A: Matrix, B: Matrix, pattern: Pattern) -> Matrix:
+F64, F32, BF16 = 0, 1, 2
+
+
+def multiply_truncate_mixed(prec: int, alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix,
+                            row_begin: int = 0, row_end: Optional[int] = None) -> None:
+    """C <- alpha mask(A B) + beta C with inputs rounded to FP32 (prec 1) or BF16 (prec 2),
+    FP32 fused multiply-add accumulation in (k, m) order, FP64 output."""
+    if prec == F64:
+        return multiply_truncate(alpha, A, B, beta, C, row_begin, row_end)
+    n = C.pattern.natoms
+    if not (A.pattern.natoms == B.pattern.natoms == n and A.b == B.b == C.b):
+        raise ValueError("pattern mismatch")
+    if row_end is None:
+        row_end = n
+    _lib().orc_multiply_mixed(n, C.b, int(prec), float(alpha),
+                              _p(A.pattern.rowptr), _p(A.pattern.cols), _p(A.blocks),
+                              _p(B.pattern.rowptr), _p(B.pattern.cols), _p(B.blocks),
+                              float(beta), _p(C.pattern.rowptr), _p(C.pattern.cols), _p(C.blocks),
+                              int(row_begin), int(row_end))
+
+
+def round_bf16(x: float) -> float:
+    """FP32 -> BF16 -> FP32, round to nearest even (the oracle's rounding)."""
+    return float(_lib().orc_round_bf16(float(x)))
+
+
+def product(A: Matrix, B: Matrix, pattern: Pattern, prec: int = F64) -> Matrix:
     C = Matrix(pattern, A.b)
-    multiply_truncate(1.0, A, B, 0.0, C)
+    multiply_truncate_mixed(prec, 1.0, A, B, 0.0, C)
     return C
 
 
@@ -403,6 +434,7 @@ class LNVState:
     tol_E: float
     PX: Pattern
     PZG: Pattern
+    prec: int = 0                      # product precision: F64, F32 or BF16
     n: int = 0
     E_prev: float = float("nan")
     D_prev: Optional[Matrix] = None
@@ -413,7 +445,7 @@ class LNVState:
 
 def lnv_init(S: Matrix, H: Matrix, Z: Matrix, l_pattern: Pattern, n_electrons: float,
              mode: int = CANONICAL, mu: float = 0.0, tol_E: float = 1e-8,
-             L0: Optional[Matrix] = None) -> LNVState:
+             L0: Optional[Matrix] = None, prec: int = F64) -> LNVState:
     """Set up the minimisation.  Without L0 the start is L0 = c mask_L(Z), c from
     the cubic N(c Z) = N_e (t_m = Tr[(Z S)^m], T = Z S exact on P(r_Z + r_S))."""
     r_x = l_pattern.cutoff + max(S.pattern.cutoff, H.pattern.cutoff)
@@ -431,22 +463,31 @@ def lnv_init(S: Matrix, H: Matrix, Z: Matrix, l_pattern: Pattern, n_electrons: f
     else:
         L = mask_copy(L0, l_pattern)
     return LNVState(S=S, H=H, Z=Z, L=L, n_electrons=n_electrons, mode=mode, mu=mu,
-                    tol_E=tol_E, PX=PX, PZG=PZG)
+                    tol_E=tol_E, PX=PX, PZG=PZG, prec=prec)
+
+
+def lnv_restart(st: LNVState, prec: int) -> None:
+    """Keep L, clear the conjugate-gradient history, switch the product precision
+    (the FP64 refinement after a low-precision stage)."""
+    st.prec = prec
+    st.n = 0
+    st.E_prev = float("nan")
+    st.D_prev = st.g_prev = st.Mg_prev = None
 
 
 def _precondition(st: LNVState, G: Matrix) -> Matrix:
     """M(G) = sym(mask_L((Z G) Z)): the S^-1-contravariant form of a gradient."""
-    ZG = product(st.Z, G, st.PZG)
-    return symmetrize(product(ZG, st.Z, st.L.pattern))
+    ZG = product(st.Z, G, st.PZG, st.prec)
+    return symmetrize(product(ZG, st.Z, st.L.pattern, st.prec))
 
 
 def lnv_energy_terms(st: LNVState):
     """X = L S, Y = L H, W = mask(X X), U = mask(Y X) on P_X and E, N from traces."""
-    PX = st.PX
-    X = product(st.L, st.S, PX)
-    Y = product(st.L, st.H, PX)
-    W = product(X, X, PX)
-    U = product(Y, X, PX)
+    PX, pr = st.PX, st.prec
+    X = product(st.L, st.S, PX, pr)
+    Y = product(st.L, st.H, PX, pr)
+    W = product(X, X, PX, pr)
+    U = product(Y, X, PX, pr)
     E = 2.0 * (3.0 * trace_product(X, Y) - 2.0 * trace_product(W, Y))
     N = 2.0 * (3.0 * trace_product(X, X) - 2.0 * trace_product(W, X))
     return X, Y, W, U, E, N
@@ -457,12 +498,12 @@ def lnv_gradients(st: LNVState, X, W, U):
 
     These are dE/dL and dN/dL for E = 2 Tr[(3LSL - 2LSLSL) H], N = 2 Tr[(3LSL - 2LSLSL) S].
     """
-    PL = st.L.pattern
-    HX = product(st.H, X, PL)
-    HW = product(st.H, W, PL)
-    SU = product(st.S, U, PL)
-    SX = product(st.S, X, PL)
-    SW = product(st.S, W, PL)
+    PL, pr = st.L.pattern, st.prec
+    HX = product(st.H, X, PL, pr)
+    HW = product(st.H, W, PL, pr)
+    SU = product(st.S, U, PL, pr)
+    SX = product(st.S, X, PL, pr)
+    SW = product(st.S, W, PL, pr)
     HXt, HWt = transpose(HX), transpose(HW)
     GE = 6.0 * (HX.blocks + HXt.blocks) - 4.0 * (HW.blocks + HWt.blocks) - 4.0 * SU.blocks
     GN = 12.0 * (SX.blocks - SW.blocks)
@@ -497,12 +538,12 @@ def lnv_step(st: LNVState) -> LNVResult:
         D = Matrix(PL, b, D.blocks - (dot(GN, D) / gn_pn) * PN.blocks)
 
     # exact line search along L + a D: X(a) = X + a X_D, Y(a) = Y + a Y_D
-    PX = st.PX
-    XD = product(D, st.S, PX)
-    YD = product(D, st.H, PX)
-    Q = product(XD, XD, PX)
+    PX, pr = st.PX, st.prec
+    XD = product(D, st.S, PX, pr)
+    YD = product(D, st.H, PX, pr)
+    Q = product(XD, XD, PX, pr)
     X1 = Matrix(PX, b, X.blocks + XD.blocks)
-    W1 = product(X1, X1, PX)
+    W1 = product(X1, X1, PX, pr)
     M1 = Matrix(PX, b, W1.blocks - W.blocks - Q.blocks)   # X XD + XD X
     tp = trace_product
     f = [tp(X, Y), tp(XD, Y) + tp(X, YD), tp(XD, YD), 0.0]
@@ -539,6 +580,51 @@ def lnv_step(st: LNVState) -> LNVResult:
     res = LNVResult(E, Omega, N, mu, a, dE, converged, OK, beta, tuple(c))
     st.history.append(res)
     return res
+
+
+def lnv_solve(st: LNVState, stages) -> dict:
+    """A precision schedule, stage by stage: lnv_step in stage precision until
+    |dE| < tol (tol > 0), or E fails to decrease (stop_on_rise), or max_iter steps;
+    later stages keep L and restart the conjugate gradients."""
+    out = dict(status=OK, converged=False, iterations=[], E=float("nan"), N=float("nan"))
+    for s, (prec, max_iter, tol, rise) in enumerate(stages):
+        if s > 0:
+            lnv_restart(st, prec)
+        else:
+            st.prec = prec
+        stop, it = False, 0
+        while it < max_iter and not stop:
+            r = lnv_step(st)
+            it += 1
+            out["E"], out["N"] = r.E, r.N
+            if r.status != OK:
+                out["status"] = r.status
+                out["iterations"].append(it)
+                return out
+            if st.n > 1:
+                if tol > 0 and abs(r.dE) < tol:
+                    stop = True
+                if rise and not (r.dE < 0.0):
+                    stop = True
+        out["iterations"].append(it)
+        if s == len(stages) - 1:
+            out["converged"] = stop or tol <= 0
+    return out
+
+
+def idempotency_error(st: LNVState) -> float:
+    """e = ||mask_X(KS KS) - KS||_F / ||KS||_F with KS = 3W - 2 mask_X(W X) on P_X.
+
+    KS = 3(LS)^2 - 2(LS)^3; for an idempotent K (K S K = K) KS is a projector.
+    Products in FP64 whatever the state's precision."""
+    PX = st.PX
+    X = product(st.L, st.S, PX)
+    W = product(X, X, PX)
+    WX = product(W, X, PX)
+    KS = Matrix(PX, st.L.b, 3.0 * W.blocks - 2.0 * WX.blocks)
+    KS2 = product(KS, KS, PX)
+    num = float(np.linalg.norm((KS2.blocks - KS.blocks).ravel()))
+    return num / float(np.linalg.norm(KS.blocks.ravel()))
 
 
 def density_matrix(st: LNVState, pattern: Pattern) -> Matrix:

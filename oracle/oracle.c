@@ -200,3 +200,83 @@ double orc_trace_product(int n, int b,
     free(part);
     return total;
 }
+
+/* ---------------------------------------------------------------------------
+ * Mixed precision: each input element rounded to FP32 or BF16 (round to
+ * nearest, ties to even), products accumulated in FP32 with fused
+ * multiply-adds over k ascending, then m ascending, per output element;
+ * the FP32 sum is widened exactly to FP64 and C <- alpha sum + beta C in FP64.
+ * prec: 1 = FP32, 2 = BF16.
+ */
+static float round_bf16(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {          /* Inf stays Inf; NaN stays a (quiet) NaN */
+        if (u & 0x007fffffu) u |= 0x00400000u;
+        u &= 0xffff0000u;
+    } else {
+        uint32_t lsb = (u >> 16) & 1u;
+        u += 0x7fffu + lsb;
+        u &= 0xffff0000u;
+    }
+    float y;
+    memcpy(&y, &u, 4);
+    return y;
+}
+
+float orc_round_bf16(float x) { return round_bf16(x); }
+
+static float round_in(double x, int prec)
+{
+    float f = (float)x;
+    return prec == 2 ? round_bf16(f) : f;
+}
+
+void orc_multiply_mixed(int n, int b, int prec, double alpha,
+                        const int64_t *rpA, const int32_t *cA, const double *vA,
+                        const int64_t *rpB, const int32_t *cB, const double *vB,
+                        double beta,
+                        const int64_t *rpC, const int32_t *cC, double *vC,
+                        int row_begin, int row_end)
+{
+    const int bb = b * b;
+#pragma omp parallel
+    {
+        int64_t *where = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        int64_t maxrow = 0;
+        for (int i = row_begin; i < row_end; ++i)
+            if (rpC[i + 1] - rpC[i] > maxrow) maxrow = rpC[i + 1] - rpC[i];
+        float *acc = (float *)malloc(sizeof(float) * (size_t)(maxrow > 0 ? maxrow : 1) * bb);
+        float a[256], bk[256];
+        for (int j = 0; j < n; ++j) where[j] = -1;
+#pragma omp for schedule(dynamic, 1)
+        for (int i = row_begin; i < row_end; ++i) {
+            int64_t c0 = rpC[i], c1 = rpC[i + 1];
+            for (int64_t s = c0; s < c1; ++s) where[cC[s]] = s - c0;
+            memset(acc, 0, sizeof(float) * (size_t)(c1 - c0) * bb);
+            for (int64_t sa = rpA[i]; sa < rpA[i + 1]; ++sa) {
+                int k = cA[sa];
+                for (int e = 0; e < bb; ++e) a[e] = round_in(vA[sa * bb + e], prec);
+                for (int64_t sb = rpB[k]; sb < rpB[k + 1]; ++sb) {
+                    int64_t t = where[cB[sb]];
+                    if (t < 0) continue;
+                    for (int e = 0; e < bb; ++e) bk[e] = round_in(vB[sb * bb + e], prec);
+                    float *c = acc + t * bb;
+                    for (int p = 0; p < b; ++p)
+                        for (int q = 0; q < b; ++q)
+                            for (int m = 0; m < b; ++m) c[p * b + q] = fmaf(a[p * b + m], bk[m * b + q], c[p * b + q]);
+                }
+            }
+            for (int64_t s = c0; s < c1; ++s) {
+                double *out = vC + s * bb;
+                const float *src = acc + (s - c0) * bb;
+                for (int e = 0; e < bb; ++e)
+                    out[e] = (beta == 0.0) ? alpha * (double)src[e] : alpha * (double)src[e] + beta * out[e];
+                where[cC[s]] = -1;
+            }
+        }
+        free(acc);
+        free(where);
+    }
+}

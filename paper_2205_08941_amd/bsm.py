@@ -71,7 +71,20 @@ class _ProductStat(ctypes.Structure):
 
 class _LNVParams(ctypes.Structure):
     _fields_ = [("n_electrons", c_double), ("mode", c_int), ("mu", c_double), ("tol_E", c_double),
-                ("init_from_z", c_int)]
+                ("init_from_z", c_int), ("product_precision", c_int)]
+
+
+MAX_STAGES = 4
+
+
+class _LNVSchedule(ctypes.Structure):
+    _fields_ = [("n_stages", c_int), ("precision", c_int * MAX_STAGES), ("max_iter", c_int * MAX_STAGES),
+                ("tol_E", c_double * MAX_STAGES), ("stop_on_rise", c_int * MAX_STAGES)]
+
+
+class _LNVSolveResult(ctypes.Structure):
+    _fields_ = [("status", c_int), ("converged", c_int), ("iterations", c_int * MAX_STAGES),
+                ("E", c_double), ("N", c_double), ("mu", c_double), ("product_flops", c_double)]
 
 
 class _LNVResult(ctypes.Structure):
@@ -105,6 +118,8 @@ EXPORTS = {
     "bsm_multiply_truncate": (c_int, [c_void_p, c_double, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                       c_double, ctypes.POINTER(_Matrix)]),
     "bsm_product_flops": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double)]),
+    "bsm_multiply_truncate_prec": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(_Matrix),
+                                           ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix)]),
     "bsm_trace_product": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                   ctypes.POINTER(c_double)]),
     "hotelling_inverse": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
@@ -115,6 +130,8 @@ EXPORTS = {
     "lnv_step": (c_int, [c_void_p, ctypes.POINTER(_LNVResult)]),
     "lnv_state_destroy": (c_int, [c_void_p]),
     "lnv_state_reset": (c_int, [c_void_p, ctypes.POINTER(_LNVParams), ctypes.POINTER(c_double)]),
+    "lnv_solve": (c_int, [c_void_p, ctypes.POINTER(_LNVSchedule), ctypes.POINTER(_LNVSolveResult)]),
+    "lnv_idempotency_error": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
 }
 
 
@@ -291,6 +308,12 @@ def multiply_truncate(alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix
     _check(_lib.bsm_multiply_truncate(C.pattern.ctx.handle, float(alpha), A.c, B.c, float(beta), C.c))
 
 
+def multiply_truncate_prec(precision: int, alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix) -> None:
+    """The product with inputs rounded to F32 or BF16 and FP32 accumulation (F64: exact)."""
+    _check(_lib.bsm_multiply_truncate_prec(C.pattern.ctx.handle, int(precision), float(alpha), A.c, B.c,
+                                           float(beta), C.c))
+
+
 def product_flops(PA: Pattern, PB: Pattern, PC: Pattern) -> float:
     f = c_double()
     _check(_lib.bsm_product_flops(PC.ctx.handle, PA.handle, PB.handle, PC.handle, ctypes.byref(f)))
@@ -366,19 +389,23 @@ class LNV:
     """LNV minimisation state over L's pattern; L (a Matrix) is updated in place."""
 
     def __init__(self, S: Matrix, H: Matrix, Z: Matrix, L: Matrix, n_electrons: float, mode: int = CANONICAL,
-                 mu: float = 0.0, tol_E: float = 1e-8, init_from_z: bool = True):
+                 mu: float = 0.0, tol_E: float = 1e-8, init_from_z: bool = True, precision: int = F64):
         self.ctx = L.pattern.ctx
         self.S, self.H, self.Z, self.L = S, H, Z, L   # keep the device buffers alive
         self.n_electrons, self.mode, self.mu, self.tol_E = float(n_electrons), int(mode), float(mu), float(tol_E)
-        prm = _LNVParams(float(n_electrons), int(mode), float(mu), float(tol_E), int(bool(init_from_z)))
+        self.precision = int(precision)
+        prm = _LNVParams(float(n_electrons), int(mode), float(mu), float(tol_E), int(bool(init_from_z)),
+                         self.precision)
         h = c_void_p()
         _check(_lib.lnv_state_create(self.ctx.handle, S.c, H.c, Z.c, L.c, ctypes.byref(prm), ctypes.byref(h)))
         self.handle = h
         self.ctx._children.add(self)
 
-    def reset(self, init_from_z: bool = True) -> float:
+    def reset(self, init_from_z: bool = True, precision: Optional[int] = None) -> float:
         """Restart from c mask_L(Z) (or the current L); returns the init products' flops."""
-        prm = _LNVParams(self.n_electrons, self.mode, self.mu, self.tol_E, int(bool(init_from_z)))
+        if precision is not None:
+            self.precision = int(precision)
+        prm = _LNVParams(self.n_electrons, self.mode, self.mu, self.tol_E, int(bool(init_from_z)), self.precision)
         f = c_double()
         _check(_lib.lnv_state_reset(self.handle, ctypes.byref(prm), ctypes.byref(f)))
         return f.value
@@ -390,6 +417,23 @@ class LNV:
             _check(code)
         return LNVResult(r.E, r.Omega, r.N, r.mu, r.alpha, r.beta, r.dE, tuple(r.c), bool(r.converged),
                          r.status, r.product_flops)
+
+    def idempotency_error(self) -> float:
+        """||mask(KS KS) - KS||_F / ||KS||_F of the current L (FP64)."""
+        e = c_double()
+        _check(_lib.lnv_idempotency_error(self.handle, ctypes.byref(e)))
+        return e.value
+
+    def solve(self, stages) -> dict:
+        """Run a precision schedule: stages = [(precision, max_iter, tol_E, stop_on_rise), ...]."""
+        sch = _LNVSchedule()
+        sch.n_stages = len(stages)
+        for k, (p, mi, tol, rise) in enumerate(stages):
+            sch.precision[k], sch.max_iter[k], sch.tol_E[k], sch.stop_on_rise[k] = int(p), int(mi), float(tol), int(rise)
+        r = _LNVSolveResult()
+        code = _lib.lnv_solve(self.handle, ctypes.byref(sch), ctypes.byref(r))
+        return dict(status=code, converged=bool(r.converged), iterations=list(r.iterations)[: len(stages)],
+                    E=r.E, N=r.N, mu=r.mu, product_flops=r.product_flops)
 
     def close(self):
         if getattr(self, "handle", None) and self.ctx.handle:

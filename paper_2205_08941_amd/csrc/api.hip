@@ -40,6 +40,16 @@ void Context::release(void *p)
     else (void)hipFree(p);
 }
 
+float *Context::scratch_f32(int which, int64_t n)
+{
+    const size_t bytes = sizeof(float) * (size_t)std::max<int64_t>(n, 1);
+    if (f32buf[which].bytes < bytes) {
+        BSM_HIP_TRY(hipStreamSynchronize(stream));   // the old buffer may still be read
+        f32buf[which] = DevBuf(this, bytes);
+    }
+    return f32buf[which].as<float>();
+}
+
 hipEvent_t Context::take_event()
 {
     if (!event_pool.empty()) {
@@ -443,6 +453,24 @@ int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const 
     Plan *plan = get_plan(&ctx->c, A->pattern, B->pattern, C->pattern);
     launch_product_f64(&ctx->c, plan, alpha, A->pattern, (const double *)A->blocks, B->pattern,
                        (const double *)B->blocks, beta, C->pattern, (double *)C->blocks);
+    return BSM_OK;
+    BSM_API_END
+}
+
+int bsm_multiply_truncate_prec(bsm_ctx ctx, int precision, double alpha, const bsm_matrix *A,
+                               const bsm_matrix *B, double beta, const bsm_matrix *C)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
+    check_matrix(A, "A");
+    check_matrix(B, "B");
+    check_matrix(C, "C");
+    check_same_shape(A, B);
+    check_same_shape(A, C);
+    BSM_REQUIRE(!overlaps(C, A) && !overlaps(C, B), BSM_EINVAL, "C overlaps A or B");
+    Plan *plan = get_plan(&ctx->c, A->pattern, B->pattern, C->pattern);
+    launch_product_mixed(&ctx->c, plan, precision, alpha, A->pattern, (const double *)A->blocks, B->pattern,
+                         (const double *)B->blocks, beta, C->pattern, (double *)C->blocks);
     return BSM_OK;
     BSM_API_END
 }

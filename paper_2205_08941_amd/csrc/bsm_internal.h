@@ -107,6 +107,9 @@ class Context {
     };
     // launches of plans whose patterns were destroyed while profiling
     std::map<std::tuple<int, int, double, double, double>, ProfAcc> retired;
+    // FP32 operand copies for mixed-precision products (grown on demand)
+    DevBuf f32buf[2];
+    float *scratch_f32(int which, int64_t n);
     hipEvent_t take_event();
     void clear_profile();
     // fold timing records of the picked plans into `retired` (they are about to go)
@@ -158,6 +161,11 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
                         const bsm_pattern_s *PC, double *C);
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
                 Plan *plan, int G);
+// prec BSM_F64: the FP64 product; BSM_F32 / BSM_BF16: operands rounded to that
+// precision, FP32 accumulation, FP64 result.
+void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha, const bsm_pattern_s *PA,
+                          const double *A, const bsm_pattern_s *PB, const double *B, double beta,
+                          const bsm_pattern_s *PC, double *C);
 int default_rows_per_wave(int b);
 
 // Traces of products Tr(A_n B_n) for up to kRedSlots pairs in one pass; A_n all

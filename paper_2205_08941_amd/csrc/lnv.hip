@@ -72,11 +72,13 @@ struct lnv_state_s {
     Mat GE, GN, PE, PN, g, Mg, D, Dprev, gprev, Mgprev, t1, t2;
     double flops = 0.0;
 
+    int prec = BSM_F64;   // precision of the step's products
+
     void mul(double alpha, const bsm_pattern_s *pa, const double *a, const bsm_pattern_s *pb, const double *b,
              double beta, const bsm_pattern_s *pc, double *cc)
     {
         Plan *plan = get_plan(c, pa, pb, pc);
-        launch_product_f64(c, plan, alpha, pa, a, pb, b, beta, pc, cc);
+        launch_product_mixed(c, plan, prec, alpha, pa, a, pb, b, beta, pc, cc);
         flops += plan->flops;
     }
     void mul(const Mat &A, const Mat &B, Mat &C) { mul(1.0, A.p, A.d(), B.p, B.d(), 0.0, C.p, C.d()); }
@@ -90,13 +92,20 @@ struct lnv_state_s {
     // t_m = Tr[(Z S)^m] (T = Z S exact on P(r_Z + r_S)) and N(c Z) = N_e.
     void reset(const lnv_params &p)
     {
+        BSM_REQUIRE(p.product_precision == BSM_F64 || p.product_precision == BSM_F32 ||
+                        p.product_precision == BSM_BF16,
+                    BSM_EINVAL, "bad product precision");
         prm = p;
         mu = p.mu;
         n = 0;
         E_prev = NAN;
         have_prev = false;
         init_flops = 0.0;
-        if (!p.init_from_z) return;
+        prec = BSM_F64;   // the initial guess is always formed in FP64
+        if (!p.init_from_z) {
+            prec = p.product_precision;
+            return;
+        }
         const bsm_pattern_s *PT = derived_pattern_cached(PZ, PZ->cutoff + PS->cutoff);
         Mat T(c, PT), T2(c, PT);
         flops = 0.0;
@@ -112,7 +121,9 @@ struct lnv_state_s {
         mask_copy(c, PZ, Z, PL, L);
         axpby(c, nelems(PL), scale, L, 0.0, L);
         BSM_HIP_TRY(hipStreamSynchronize(c->stream));
+        prec = p.product_precision;
     }
+    int step(lnv_result *res);
     double init_flops = 0.0;
 
     double dot1(const Mat &A, const Mat &B)
@@ -197,6 +208,19 @@ extern "C" int lnv_step(lnv_state *st, lnv_result *res)
 {
     try {
         BSM_REQUIRE(st && res, BSM_EINVAL, "NULL argument");
+        return st->step(res);
+    } catch (const Error &e) {
+        if (res) res->status = e.code;
+        return fail(e.code, e.msg);
+    } catch (...) {
+        return fail(BSM_EINVAL, "unknown error");
+    }
+}
+
+int lnv_state_s::step(lnv_result *res)
+{
+    lnv_state_s *st = this;
+    {
         Context *c = st->c;
         st->flops = 0.0;
         *res = lnv_result{};
@@ -339,8 +363,83 @@ extern "C" int lnv_step(lnv_state *st, lnv_result *res)
         st->have_prev = true;
         st->n += 1;
         return BSM_OK;
+    }
+}
+
+extern "C" int lnv_idempotency_error(lnv_state *st, double *e_idem)
+{
+    try {
+        BSM_REQUIRE(st && e_idem, BSM_EINVAL, "NULL argument");
+        Context *c = st->c;
+        const int saved = st->prec;
+        st->prec = BSM_F64;
+        const int64_t nx = nelems(st->PX);
+        // X = L S, W = X X, then KS = 3 W - 2 mask_X(W X) and KS2 = mask_X(KS KS), all on P_X
+        st->mul(1.0, st->PL, st->L, st->PS, st->S, 0.0, st->X.p, st->X.d());
+        st->mul(st->X, st->X, st->W);
+        st->mul(st->W, st->X, st->U);
+        axpbypcz(c, nx, 3.0, st->W.d(), -2.0, st->U.d(), 0.0, st->Q.d());
+        st->mul(st->Q, st->Q, st->W1);
+        axpby(c, nx, -1.0, st->Q.d(), 1.0, st->W1.d());
+        double d[2];
+        const double *a[2] = {st->W1.d(), st->Q.d()}, *b[2] = {st->W1.d(), st->Q.d()};
+        dots(c, 2, st->PX, a, b, d);
+        st->prec = saved;
+        *e_idem = std::sqrt(d[0]) / std::sqrt(d[1]);
+        if (!std::isfinite(*e_idem)) return fail(BSM_ENONFINITE, "idempotency error is not finite");
+        return BSM_OK;
     } catch (const Error &e) {
-        if (res) res->status = e.code;
+        return fail(e.code, e.msg);
+    } catch (...) {
+        return fail(BSM_EINVAL, "unknown error");
+    }
+}
+
+extern "C" int lnv_solve(lnv_state *st, const lnv_schedule *sch, lnv_solve_result *out)
+{
+    try {
+        BSM_REQUIRE(st && sch && out, BSM_EINVAL, "NULL argument");
+        BSM_REQUIRE(sch->n_stages >= 1 && sch->n_stages <= LNV_MAX_STAGES, BSM_EINVAL, "1..4 stages");
+        *out = lnv_solve_result{};
+        for (int s = 0; s < sch->n_stages; ++s) {
+            const int p = sch->precision[s];
+            BSM_REQUIRE(p == BSM_F64 || p == BSM_F32 || p == BSM_BF16, BSM_EINVAL, "bad stage precision");
+            BSM_REQUIRE(sch->max_iter[s] >= 0, BSM_EINVAL, "bad stage max_iter");
+            if (s > 0) {   // keep L, restart the conjugate gradients in the new precision
+                lnv_params prm = st->prm;
+                prm.init_from_z = 0;
+                prm.product_precision = p;
+                st->reset(prm);
+            } else {
+                st->prm.product_precision = p;
+                st->prec = p;
+            }
+            bool stop = false;
+            int it = 0;
+            for (; it < sch->max_iter[s] && !stop; ++it) {
+                lnv_result r{};
+                const int code = st->step(&r);
+                out->product_flops += r.product_flops;
+                out->E = r.E;
+                out->N = r.N;
+                out->mu = r.mu;
+                if (code != BSM_OK) {
+                    out->status = code;
+                    out->iterations[s] = it + 1;
+                    return code;
+                }
+                if (st->n > 1) {
+                    if (sch->tol_E[s] > 0 && std::fabs(r.dE) < sch->tol_E[s]) stop = true;
+                    if (sch->stop_on_rise[s] && !(r.dE < 0.0)) stop = true;
+                }
+            }
+            out->iterations[s] = it;
+            if (s == sch->n_stages - 1) out->converged = (stop || sch->tol_E[s] <= 0) ? 1 : 0;
+        }
+        out->status = BSM_OK;
+        return BSM_OK;
+    } catch (const Error &e) {
+        if (out) out->status = e.code;
         return fail(e.code, e.msg);
     } catch (...) {
         return fail(BSM_EINVAL, "unknown error");

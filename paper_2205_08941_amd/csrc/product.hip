@@ -49,9 +49,9 @@ __device__ inline int64_t logical_workgroup(int64_t nwg_padded)
 // Tile header, ints: rows[G] (atom ids, -1 = padding), cslot[G][JT] (slot of
 // (i_a, j) in C or -1).  Entries of tile t: ebeg[t] .. ebeg[t+1], each G + JT
 // ints: aslot[G] (slot of (i_a, k) in A or -1), bslot[JT] (slot of (k, j) in B or -1).
-template <int B, int G>
-__device__ inline void multiply_entry(const_as4<int> *entu, int64_t q, const_as4<double> *vAu, const double (&bv)[B],
-                                      bool bact, const bool (&cact)[G], double (&acc)[G][B])
+template <int B, int G, class T>
+__device__ inline void multiply_entry(const_as4<int> *entu, int64_t q, const_as4<T> *vAu, const T (&bv)[B],
+                                      bool bact, const bool (&cact)[G], T (&acc)[G][B])
 {
     constexpr int BB = B * B;
     constexpr int ES = G + 64 / B;
@@ -60,7 +60,7 @@ __device__ inline void multiply_entry(const_as4<int> *entu, int64_t q, const_as4
         const int as = entu[q * ES + a];
         if (as < 0) continue;
         if (bact && cact[a]) {
-            const_as4<double> *ap = vAu + (int64_t)as * BB;
+            const_as4<T> *ap = vAu + (int64_t)as * BB;
 #pragma unroll
             for (int r = 0; r < B; ++r)
 #pragma unroll
@@ -75,11 +75,14 @@ __device__ inline void multiply_entry(const_as4<int> *entu, int64_t q, const_as4
 // ints: aslot[G] (slot of (i_a, k) in A or -1), bslot[JT] (slot of (k, j) in B
 // or -1).  The entry array has 4 spare entries at its end, so the index
 // prefetch past a tile's last entry stays in bounds.
-template <int B, int G>
-__global__ __launch_bounds__(256) void k_product_f64(
+// T = double: FP64 product.  T = float: operands already rounded to FP32 (or to
+// BF16 and stored as FP32), FP32 fused multiply-add accumulation in the same
+// (k, m) order, the FP32 sums widened to FP64 for alpha, beta and the store.
+template <int B, int G, class T>
+__global__ __launch_bounds__(256) void k_product_sgpr(
     int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
-    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
-    const double *__restrict__ vB, double *__restrict__ vC, double alpha, double beta)
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const T *__restrict__ vA,
+    const T *__restrict__ vB, double *__restrict__ vC, double alpha, double beta)
 {
     constexpr int JT = 64 / B;
     constexpr int BB = B * B;
@@ -100,11 +103,11 @@ __global__ __launch_bounds__(256) void k_product_f64(
         cs[a] = lane_ok ? h[G + a * JT + jl] : -1;
         cact[a] = cs[a] >= 0;
     }
-    double acc[G][B];
+    T acc[G][B];
 #pragma unroll
     for (int a = 0; a < G; ++a)
 #pragma unroll
-        for (int r = 0; r < B; ++r) acc[a][r] = 0.0;
+        for (int r = 0; r < B; ++r) acc[a][r] = T(0);
 
     const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
                        ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
@@ -113,17 +116,17 @@ __global__ __launch_bounds__(256) void k_product_f64(
     const int n = (int)(e1 - e0);                  // even
     const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
     const int *entv = ent + e0 * ES + G + jl;      // this lane's B slot column
-    const_as4<double> *vAu = (const_as4<double> *)vA;
-    const double *vBc = vB + c;
+    const_as4<T> *vAu = (const_as4<T> *)vA;
+    const T *vBc = vB + c;
 
     // ping-pong buffers: entry q in ba while q+1 loads into bb, then q+1 in bb
     // while q+2 loads into ba; B slot indices run two entries ahead.
-    double ba[B], bb[B];
+    T ba[B], bb[B];
     int ia = entv[0], ib = entv[ES];
     ia = (0 < n) ? ia : -1;
     ib = (1 < n) ? ib : -1;
     {
-        const double *bp = vBc + (int64_t)max(ia, 0) * BB;
+        const T *bp = vBc + (int64_t)max(ia, 0) * BB;
 #pragma unroll
         for (int m = 0; m < B; ++m) ba[m] = bp[m * B];
     }
@@ -131,19 +134,19 @@ __global__ __launch_bounds__(256) void k_product_f64(
         int ic = entv[(int64_t)(q + 2) * ES];
         ic = (q + 2 < n) ? ic : -1;
         {
-            const double *bp = vBc + (int64_t)max(ib, 0) * BB;
+            const T *bp = vBc + (int64_t)max(ib, 0) * BB;
 #pragma unroll
             for (int m = 0; m < B; ++m) bb[m] = bp[m * B];
         }
-        multiply_entry<B, G>(entu, q, vAu, ba, ia >= 0, cact, acc);
+        multiply_entry<B, G, T>(entu, q, vAu, ba, ia >= 0, cact, acc);
         int id = entv[(int64_t)(q + 3) * ES];
         id = (q + 3 < n) ? id : -1;
         {
-            const double *bp = vBc + (int64_t)max(ic, 0) * BB;
+            const T *bp = vBc + (int64_t)max(ic, 0) * BB;
 #pragma unroll
             for (int m = 0; m < B; ++m) ba[m] = bp[m * B];
         }
-        multiply_entry<B, G>(entu, q + 1, vAu, bb, ib >= 0, cact, acc);
+        multiply_entry<B, G, T>(entu, q + 1, vAu, bb, ib >= 0, cact, acc);
         ia = ic;
         ib = id;
     }
@@ -153,10 +156,10 @@ __global__ __launch_bounds__(256) void k_product_f64(
         double *cp = vC + (int64_t)cs[a] * BB + c;
         if (beta == 0.0) {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r] + beta * cp[r * B];
         }
     }
 }
@@ -352,6 +355,30 @@ __global__ __launch_bounds__(256) void k_product_f64_dpp(
     }
 }
 
+// ---------------------------------------------------------------- operand rounding
+// FP64 -> FP32 (round to nearest even); for BF16, the FP32 value rounded again
+// to 8 significant bits (nearest even, Inf kept, NaN kept quiet), stored as FP32.
+__device__ inline float round_bf16(float x)
+{
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) {
+        if (u & 0x007fffffu) u |= 0x00400000u;
+        u &= 0xffff0000u;
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        u &= 0xffff0000u;
+    }
+    return __uint_as_float(u);
+}
+
+__global__ void k_round_copy(int64_t n, const double *__restrict__ x, float *__restrict__ y, int bf16)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float f = (float)x[e];
+    y[e] = bf16 ? round_bf16(f) : f;
+}
+
 // ---------------------------------------------------------------- planner
 __device__ inline int find_in_row(const int *__restrict__ rp, const int *__restrict__ cols, int i, int j)
 {
@@ -537,13 +564,13 @@ __global__ void k_int_to_i64(int n, const int *__restrict__ in, int64_t *__restr
     if (i < n) out[i] = in[i];
 }
 
-template <int B, int G>
-void launch_bg(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
+template <int B, int G, class T = double>
+void launch_bg(hipStream_t st, const Plan *plan, const T *A, const T *Bm, double *C, double alpha,
                double beta)
 {
     const int64_t nwg = (plan->ntiles + kWaves - 1) / kWaves;
     const int64_t nwg_padded = ((nwg + kXcd - 1) / kXcd) * kXcd;
-    k_product_f64<B, G><<<(unsigned)nwg_padded, 64 * kWaves, 0, st>>>(
+    k_product_sgpr<B, G, T><<<(unsigned)nwg_padded, 64 * kWaves, 0, st>>>(
         plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
         plan->ent.as<int>(), A, Bm, C, alpha, beta);
 }
@@ -576,6 +603,18 @@ void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *B
         case 2: launch_bg<B, 2>(st, plan, A, Bm, C, alpha, beta); break;
         case 4: launch_bg<B, 4>(st, plan, A, Bm, C, alpha, beta); break;
         case 8: launch_bg<B, 8>(st, plan, A, Bm, C, alpha, beta); break;
+        default: throw Error{BSM_EINVAL, "rows per wave must be 2, 4 or 8"};
+    }
+}
+
+template <int B>
+void launch_b32(hipStream_t st, const Plan *plan, const float *A, const float *Bm, double *C, double alpha,
+                double beta)
+{
+    switch (plan->G) {
+        case 2: launch_bg<B, 2, float>(st, plan, A, Bm, C, alpha, beta); break;
+        case 4: launch_bg<B, 4, float>(st, plan, A, Bm, C, alpha, beta); break;
+        case 8: launch_bg<B, 8, float>(st, plan, A, Bm, C, alpha, beta); break;
         default: throw Error{BSM_EINVAL, "rows per wave must be 2, 4 or 8"};
     }
 }
@@ -688,6 +727,42 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
     switch (PC->b) {
 #define X(b) \
     case b: launch_b<b>(st, plan, A, Bm, C, alpha, beta, ctx->zero_block.as<double>()); break;
+        BSM_FOR_EACH_B(X)
+#undef X
+        default: throw Error{BSM_EINVAL, "b must be in 1..16"};
+    }
+    BSM_HIP_TRY(hipGetLastError());
+    if (ctx->profiling) {
+        BSM_HIP_TRY(hipEventRecord(rec.stop, st));
+        ctx->prof.push_back(rec);
+    }
+}
+
+void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha, const bsm_pattern_s *PA,
+                          const double *A, const bsm_pattern_s *PB, const double *Bm, double beta,
+                          const bsm_pattern_s *PC, double *C)
+{
+    if (prec == BSM_F64) {
+        launch_product_f64(ctx, plan, alpha, PA, A, PB, Bm, beta, PC, C);
+        return;
+    }
+    BSM_REQUIRE(prec == BSM_F32 || prec == BSM_BF16, BSM_EINVAL, "precision must be F64, F32 or BF16");
+    if (plan->ntiles == 0) return;
+    hipStream_t st = ctx->stream;
+    const int64_t na = nelems(PA), nb = nelems(PB);
+    float *a32 = ctx->scratch_f32(0, na), *b32 = ctx->scratch_f32(1, nb);
+    const int bf = prec == BSM_BF16 ? 1 : 0;
+    k_round_copy<<<(unsigned)((na + 255) / 256), 256, 0, st>>>(na, A, a32, bf);
+    k_round_copy<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, Bm, b32, bf);
+    Context::ProfRec rec{plan, nullptr, nullptr};
+    if (ctx->profiling) {
+        rec.start = ctx->take_event();
+        rec.stop = ctx->take_event();
+        BSM_HIP_TRY(hipEventRecord(rec.start, st));
+    }
+    switch (PC->b) {
+#define X(b) \
+    case b: launch_b32<b>(st, plan, a32, b32, C, alpha, beta); break;
         BSM_FOR_EACH_B(X)
 #undef X
         default: throw Error{BSM_EINVAL, "b must be in 1..16"};

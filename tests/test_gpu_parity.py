@@ -358,3 +358,57 @@ def test_w_class_product_4096_sampled(bsm, ctx):
         O.multiply_truncate(1.0, O.Matrix(o16, 9, x), O.Matrix(o16, 9, y), 0.0, Co, r, r + 1)
         sl = slice(o16.rowptr[r], o16.rowptr[r + 1])
         assert rel_err(g[sl], Co.blocks[sl]) < 1e-12, r
+
+
+# ------------------------------------------------------------------ mixed precision and diagnostics
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("b", [4, 9])
+def test_mixed_product_parity(bsm, ctx, prec, b):
+    """FP32 / BF16-rounded operands, FP32 accumulation: the oracle's result up to
+    the FP64 epilogue (same rounding, same accumulation order)."""
+    s = SYSTEMS["si256_disp"]()
+    say(f"mixed product prec={prec} b={b}")
+    gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
+    for n, (ra, rb, rc) in enumerate([(6, 8, 14), (14, 8, 6)]):
+        a = synth.random_blocks(op[ra].nnz, b, 70 + n)
+        bb = synth.random_blocks(op[rb].nnz, b, 80 + n)
+        c0 = synth.random_blocks(op[rc].nnz, b, 90 + n)
+        A, B, C = gmat(bsm, gp[ra], a), gmat(bsm, gp[rb], bb), gmat(bsm, gp[rc], c0)
+        bsm.multiply_truncate_prec(prec, 0.5, A, B, 0.25, C)
+        Co = O.Matrix(op[rc], b, c0.copy())
+        O.multiply_truncate_mixed(prec, 0.5, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), 0.25, Co)
+        assert rel_err(host(C), Co.blocks) < 1e-14
+
+
+@pytest.mark.parametrize("b", [4, 9])
+def test_idempotency_error_parity(bsm, ctx, b):
+    s = synth.make_system("l", 2, b, synth.SMALL_CUTOFFS, 2205)
+    g, L, st = _lnv_pair(bsm, ctx, s)
+    for _ in range(6):
+        g.step()
+        O.lnv_step(st)
+    eg, eo = g.idempotency_error(), O.idempotency_error(st)
+    assert eg == pytest.approx(eo, rel=1e-8)
+    assert g.step().E == pytest.approx(O.lnv_step(st).E, rel=1e-10)   # the diagnostic left the state intact
+
+
+@pytest.mark.parametrize("b", [4, 9])
+def test_mixed_schedule_reaches_fp64_energy(bsm, ctx, b):
+    """BF16 then FP32 products (FP64 traces), then 3 FP64 steps: the energy of the
+    FP64 oracle's converged solve to better than 1e-6 Ha/atom, on GPU and oracle alike."""
+    s = synth.make_system("l", 2, b, synth.SMALL_CUTOFFS, 2205)
+    say(f"mixed schedule b={b}")
+    g, L, st = _lnv_pair(bsm, ctx, s)
+    o_ref = O.lnv_init(st.S, st.H, st.Z, st.L.pattern, s.n_electrons, tol_E=1e-11)
+    for _ in range(100):
+        if O.lnv_step(o_ref).converged:
+            break
+    E_ref = o_ref.E_prev
+    stages = [(2, 30, 0.0, True), (1, 60, 1e-6, True), (0, 3, 0.0, False)]
+    rg = g.solve(stages)
+    ro = O.lnv_solve(st, stages)
+    assert rg["status"] == 0 and ro["status"] == 0 and rg["converged"]
+    assert abs(rg["E"] - E_ref) / 64 < 1e-6 and abs(ro["E"] - E_ref) / 64 < 1e-6
+    assert abs(rg["E"] - ro["E"]) / 64 < 1e-6
+    assert rg["product_flops"] > 0
