@@ -195,6 +195,35 @@ int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const 
  * FP64 traces and refinement (spec extension, not in the paper). */
 int bsm_multiply_truncate_prec(bsm_ctx ctx, int precision, double alpha, const bsm_matrix *A,
                                const bsm_matrix *B, double beta, const bsm_matrix *C);
+/* ---- many products in one persistent launch (spec extension) --------
+ * A batch of independent products C_p <- alpha_p mask(A_p B_p) + beta_p C_p,
+ * b = 4 or 9 (e.g. one per system of a batch of uneven systems), runs as one
+ * launch of resident wavefronts that take tiles from work queues until the list
+ * is exhausted.  Results equal the separate products bit for bit (tiles write
+ * disjoint outputs).  The schedule (bsm_batch_config) is chosen by
+ * bsm_batch_tune, which times every candidate on the batch itself. */
+typedef struct bsm_batch_s *bsm_batch;
+enum { BSM_ORDER_BY_PRODUCT = 0, BSM_ORDER_HEAVY_FIRST = 1, BSM_ORDER_INTERLEAVE = 2 };
+typedef struct {
+    int order;          /* BSM_ORDER_*: work-list order */
+    int waves_per_cu;   /* resident wavefronts per CU: 4, 8, ..., 32 */
+    int queues;         /* 1 (one global queue) or 8 (one per XCD, equal-weight slices) */
+} bsm_batch_config;
+/* n products; A, B, C arrays of n matrices (C_p must not overlap A_p or B_p),
+ * alpha, beta arrays of n.  precision: BSM_F64, BSM_F32 or BSM_BF16 (as in
+ * bsm_multiply_truncate_prec).  Builds (or reuses) each product's plan.  The
+ * matrices must outlive the batch.  Errors: BSM_EINVAL (b not 4 or 9, plan not
+ * at 4 rows per wave), BSM_EPATTERN, BSM_ENOMEM. */
+int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *B, const bsm_matrix *C,
+                     const double *alpha, const double *beta, int precision, bsm_batch *out);
+/* Queue the batch on the context stream; cfg NULL = the tuned (or default) schedule. */
+int bsm_batch_run(bsm_batch batch, const bsm_batch_config *cfg);
+/* Time every candidate schedule (3 orders x {1, 8} queues x {4, 8, 16} waves
+ * per CU), `reps` runs each, keep the fastest.  Runs the batch many times. */
+int bsm_batch_tune(bsm_batch batch, int reps, bsm_batch_config *best, double *best_ms);
+int bsm_batch_flops(bsm_batch batch, double *flops);
+int bsm_batch_destroy(bsm_batch batch);
+
 /* Algorithmic flops of mask_{P_C}(A B): 2 b^3 per block triple (i, k, j). */
 int bsm_product_flops(bsm_ctx ctx, bsm_pattern PA, bsm_pattern PB, bsm_pattern PC, double *flops);
 

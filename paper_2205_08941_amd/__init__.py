@@ -2,7 +2,8 @@
 products, traces, Hotelling S^-1 and LNV minimisation in hand-written HIP,
 behind the C ABI of include/bsm.h.  Importing this package loads libbsm.so
 and fails if it has not been built; there is no CPU fallback."""
-from .bsm import (BSMError, Context, Pattern, Matrix, LNV, LNVResult, HotellingResult, fill_blocks,
+from .bsm import (BSMError, Context, Pattern, Matrix, LNV, Batch, ORDER_BY_PRODUCT, ORDER_HEAVY_FIRST,
+                  ORDER_INTERLEAVE, LNVResult, HotellingResult, fill_blocks,
                   multiply_truncate, multiply_truncate_prec, product_flops, trace_product, dot, axpby, symmetrize, mask_copy,
                   set_identity, hotelling_inverse, load_library, LIB_PATH, EXPORTS,
                   OK, EINVAL, ENOMEM, EPATTERN, EHIP, ENONFINITE, EDIVERGED, ENOTCONV, ERUNAWAY,

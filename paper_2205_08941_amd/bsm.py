@@ -54,6 +54,13 @@ class _PatternInfo(ctypes.Structure):
                 ("tmap", c_void_p), ("diag", c_void_p), ("pos", c_void_p)]
 
 
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("order", c_int), ("waves_per_cu", c_int), ("queues", c_int)]
+
+
+ORDER_BY_PRODUCT, ORDER_HEAVY_FIRST, ORDER_INTERLEAVE = 0, 1, 2
+
+
 class _HotParams(ctypes.Structure):
     _fields_ = [("max_iter", c_int), ("tol", c_double), ("init_given", c_int)]
 
@@ -122,6 +129,13 @@ EXPORTS = {
                                            ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix)]),
     "bsm_trace_product": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                   ctypes.POINTER(c_double)]),
+    "bsm_batch_create": (c_int, [c_void_p, c_int, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                                 ctypes.POINTER(_Matrix), ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                 c_int, ctypes.POINTER(c_void_p)]),
+    "bsm_batch_run": (c_int, [c_void_p, ctypes.POINTER(_BatchConfig)]),
+    "bsm_batch_tune": (c_int, [c_void_p, c_int, ctypes.POINTER(_BatchConfig), ctypes.POINTER(c_double)]),
+    "bsm_batch_flops": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
+    "bsm_batch_destroy": (c_int, [c_void_p]),
     "hotelling_inverse": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                   ctypes.POINTER(_HotParams), ctypes.POINTER(_HotResult)]),
     "lnv_state_create": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
@@ -229,8 +243,8 @@ class Context:
         self._keep.pop(ptr, None)
 
     def close(self):
-        # solver states before the patterns they point into
-        for ch in sorted(self._children, key=lambda o: not isinstance(o, LNV)):
+        # solver states and batches before the patterns they point into
+        for ch in sorted(self._children, key=lambda o: not isinstance(o, (LNV, Batch))):
             ch.close()
         if self.handle:
             _lib.bsm_ctx_destroy(self.handle)
@@ -346,6 +360,48 @@ def mask_copy(src: Matrix, dst: Matrix) -> None:
 
 def set_identity(M: Matrix, alpha: float = 1.0) -> None:
     _check(_lib.bsm_set_identity(M.pattern.ctx.handle, M.c, float(alpha)))
+
+
+class Batch:
+    """Independent products C_p <- alpha_p mask(A_p B_p) + beta_p C_p in one persistent launch."""
+
+    def __init__(self, ctx: Context, triples, alpha=1.0, beta=0.0, precision: int = F64):
+        self.ctx = ctx
+        self.triples = list(triples)          # keep the matrices alive
+        n = len(self.triples)
+        A = (_Matrix * n)(*[t[0]._c for t in self.triples])
+        B = (_Matrix * n)(*[t[1]._c for t in self.triples])
+        C = (_Matrix * n)(*[t[2]._c for t in self.triples])
+        al = (c_double * n)(*([float(alpha)] * n if np.isscalar(alpha) else [float(a) for a in alpha]))
+        be = (c_double * n)(*([float(beta)] * n if np.isscalar(beta) else [float(b) for b in beta]))
+        h = c_void_p()
+        _check(_lib.bsm_batch_create(ctx.handle, n, A, B, C, al, be, int(precision), ctypes.byref(h)))
+        self.handle = h
+        ctx._children.add(self)
+        f = c_double()
+        _check(_lib.bsm_batch_flops(h, ctypes.byref(f)))
+        self.flops = f.value
+
+    def run(self, order: Optional[int] = None, waves_per_cu: int = 8, queues: int = 1) -> None:
+        if order is None:
+            _check(_lib.bsm_batch_run(self.handle, None))
+        else:
+            cfg = _BatchConfig(int(order), int(waves_per_cu), int(queues))
+            _check(_lib.bsm_batch_run(self.handle, ctypes.byref(cfg)))
+
+    def tune(self, reps: int = 1):
+        cfg, ms = _BatchConfig(), c_double()
+        _check(_lib.bsm_batch_tune(self.handle, int(reps), ctypes.byref(cfg), ctypes.byref(ms)))
+        return dict(order=cfg.order, waves_per_cu=cfg.waves_per_cu, queues=cfg.queues), ms.value
+
+    def close(self):
+        if getattr(self, "handle", None) and self.ctx.handle:
+            _lib.bsm_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
 
 @dataclass

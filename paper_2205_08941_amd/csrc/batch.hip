@@ -1,0 +1,357 @@
+// Many independent products in one persistent launch, with a tile schedule
+// chosen by measurement.
+//
+// A batch holds up to thousands of truncated products (C_p <- alpha_p
+// mask(A_p B_p) + beta_p C_p), typically from independent systems of uneven
+// size and orbital count (b = 4 or 9).  Every product keeps its own plan; the
+// batch concatenates their tiles into one work list.  A fixed grid of
+// wavefronts stays resident and takes tiles from work queues by an atomic
+// counter until the list is exhausted (every wave reaches the exit test).
+// Tiles write disjoint outputs, so the result does not depend on which wave
+// takes which tile: it equals the separate products bit for bit.
+//
+// Schedule knobs, measured by bsm_batch_tune: the order of the work list (by
+// product, heaviest tile first, or products interleaved), the resident waves
+// per CU, and one global queue or one queue per XCD (each XCD then works
+// through a contiguous, equally weighted slice of the list).
+#include "bsm_internal.h"
+#include "tiles.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+namespace bsm {
+
+// product kinds handled by the persistent kernel
+enum { kKindF64Dpp9 = 0, kKindF64Dpp4 = 1, kKindF32b9 = 2, kKindF32b4 = 3 };
+
+struct BatchDesc {
+    int kind;
+    int pad;
+    const int *hdr;
+    const int64_t *ebeg;
+    const int *ent;
+    const void *A;
+    const void *B;
+    double *C;
+    double alpha, beta;
+};
+
+namespace {
+
+constexpr int kCUs = 256;
+
+__global__ void k_zero_counters(int n, unsigned *c)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_product_batch(const BatchDesc *__restrict__ desc, const int2 *__restrict__ items,
+                                                       const int64_t *__restrict__ qbeg, int nq,
+                                                       unsigned *__restrict__ counters, const double *__restrict__ zblk)
+{
+    const int lane = threadIdx.x & 63;
+    const int q = (int)(blockIdx.x % (unsigned)nq);   // workgroups are dealt round-robin to the XCDs
+    const int64_t base = qbeg[q];
+    const int64_t len = qbeg[q + 1] - base;
+    while (true) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(&counters[q], 1u);
+        t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl((int)t, 0, 64));
+        if ((int64_t)t >= len) break;
+        const int2 it = items[base + t];
+        const int p = __builtin_amdgcn_readfirstlane(it.x);
+        const BatchDesc d = desc[p];
+        switch (__builtin_amdgcn_readfirstlane(d.kind)) {
+            case kKindF64Dpp9:
+                tile_dpp<9, 4>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A, (const double *)d.B, zblk, d.C,
+                               d.alpha, d.beta);
+                break;
+            case kKindF64Dpp4:
+                tile_dpp<4, 4>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A, (const double *)d.B, zblk, d.C,
+                               d.alpha, d.beta);
+                break;
+            case kKindF32b9:
+                tile_sgpr<9, 4, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A, (const float *)d.B, d.C,
+                                       d.alpha, d.beta);
+                break;
+            default:
+                tile_sgpr<4, 4, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A, (const float *)d.B, d.C,
+                                       d.alpha, d.beta);
+                break;
+        }
+    }
+}
+
+__global__ void k_round_copy_b(int64_t n, const double *__restrict__ x, float *__restrict__ y, int bf16)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float f = (float)x[e];
+    if (bf16) {
+        unsigned u = __float_as_uint(f);
+        if ((u & 0x7f800000u) == 0x7f800000u) {
+            if (u & 0x007fffffu) u |= 0x00400000u;
+            u &= 0xffff0000u;
+        } else {
+            u += 0x7fffu + ((u >> 16) & 1u);
+            u &= 0xffff0000u;
+        }
+        f = __uint_as_float(u);
+    }
+    y[e] = f;
+}
+
+}  // namespace
+}  // namespace bsm
+
+using namespace bsm;
+
+struct bsm_batch_s {
+    Context *c = nullptr;
+    int n = 0;
+    int prec = BSM_F64;
+    std::vector<Plan *> plans;
+    std::vector<const bsm_pattern_s *> pa, pb, pc;
+    std::vector<const double *> A, B;
+    std::vector<double *> C;
+    std::vector<int64_t> a_n, b_n;           // elements of each operand
+    std::vector<DevBuf> a32, b32;           // rounded operand copies (FP32 / BF16 batches)
+    std::vector<std::vector<int64_t>> work;  // entries per tile, per product
+    DevBuf desc, items, qbeg, counters;
+    double flops = 0.0;
+    int64_t ntiles = 0;
+    bool tuned = false;
+    bsm_batch_config best{};
+    bsm_batch_config built{-1, -1, -1};
+
+    void build_schedule(const bsm_batch_config &cfg);
+    void run(const bsm_batch_config &cfg);
+};
+
+void bsm_batch_s::build_schedule(const bsm_batch_config &cfg)
+{
+    if (cfg.order == built.order && cfg.queues == built.queues) return;
+    // each product's own launch order of its tiles (XCD-friendly interleaving of row groups)
+    std::vector<std::vector<int>> order(n);
+    for (int p = 0; p < n; ++p) {
+        order[p].resize((size_t)plans[p]->ntiles);
+        if (plans[p]->ntiles > 0)
+            BSM_HIP_TRY(hipMemcpy(order[p].data(), plans[p]->order.ptr, sizeof(int) * (size_t)plans[p]->ntiles,
+                                  hipMemcpyDeviceToHost));
+    }
+    std::vector<int2> list;   // (product, tile id)
+    list.reserve((size_t)ntiles);
+    if (cfg.order == BSM_ORDER_BY_PRODUCT) {
+        for (int p = 0; p < n; ++p)
+            for (int64_t t = 0; t < plans[p]->ntiles; ++t) list.push_back(make_int2(p, order[p][t]));
+    } else if (cfg.order == BSM_ORDER_INTERLEAVE) {
+        int64_t longest = 0;
+        for (int p = 0; p < n; ++p) longest = std::max(longest, plans[p]->ntiles);
+        for (int64_t t = 0; t < longest; ++t)
+            for (int p = 0; p < n; ++p)
+                if (t < plans[p]->ntiles) list.push_back(make_int2(p, order[p][t]));
+    } else {   // heaviest tile first (longest-processing-time order for the dynamic queue)
+        for (int p = 0; p < n; ++p)
+            for (int64_t t = 0; t < plans[p]->ntiles; ++t) list.push_back(make_int2(p, order[p][t]));
+        std::stable_sort(list.begin(), list.end(), [&](const int2 &x, const int2 &y) {
+            const double wx = (double)work[x.x][x.y] * plans[x.x]->b * plans[x.x]->b;
+            const double wy = (double)work[y.x][y.y] * plans[y.x]->b * plans[y.x]->b;
+            return wx > wy;
+        });
+    }
+    // queues: contiguous slices of the list with equal weight
+    const int nq = std::max(1, cfg.queues);
+    std::vector<int64_t> qb(nq + 1, 0);
+    double total = 0.0;
+    std::vector<double> w(list.size());
+    for (size_t k = 0; k < list.size(); ++k) {
+        w[k] = (double)(work[list[k].x][list[k].y] + 1) * plans[list[k].x]->b * plans[list[k].x]->b;
+        total += w[k];
+    }
+    double acc = 0.0;
+    int qi = 1;
+    for (size_t k = 0; k < list.size() && qi < nq; ++k) {
+        acc += w[k];
+        while (qi < nq && acc >= total * qi / nq) qb[qi++] = (int64_t)k + 1;
+    }
+    while (qi < nq) qb[qi++] = (int64_t)list.size();
+    qb[nq] = (int64_t)list.size();
+    items = DevBuf(c, sizeof(int2) * std::max<size_t>(1, list.size()));
+    qbeg = DevBuf(c, sizeof(int64_t) * (nq + 1));
+    if (!list.empty())
+        BSM_HIP_TRY(hipMemcpyAsync(items.ptr, list.data(), sizeof(int2) * list.size(), hipMemcpyHostToDevice, c->stream));
+    BSM_HIP_TRY(hipMemcpyAsync(qbeg.ptr, qb.data(), sizeof(int64_t) * (nq + 1), hipMemcpyHostToDevice, c->stream));
+    BSM_HIP_TRY(hipStreamSynchronize(c->stream));
+    built = cfg;
+}
+
+void bsm_batch_s::run(const bsm_batch_config &cfg)
+{
+    BSM_REQUIRE(cfg.order >= 0 && cfg.order <= 2, BSM_EINVAL, "bad batch order");
+    BSM_REQUIRE(cfg.waves_per_cu >= 4 && cfg.waves_per_cu <= 32 && cfg.waves_per_cu % 4 == 0, BSM_EINVAL,
+                "waves per CU must be 4..32, a multiple of 4");
+    BSM_REQUIRE(cfg.queues == 1 || cfg.queues == 8, BSM_EINVAL, "queues must be 1 or 8");
+    build_schedule(cfg);
+    hipStream_t st = c->stream;
+    if (prec != BSM_F64) {
+        for (int p = 0; p < n; ++p) {
+            k_round_copy_b<<<(unsigned)((a_n[p] + 255) / 256), 256, 0, st>>>(a_n[p], A[p], a32[p].as<float>(),
+                                                                             prec == BSM_BF16);
+            k_round_copy_b<<<(unsigned)((b_n[p] + 255) / 256), 256, 0, st>>>(b_n[p], B[p], b32[p].as<float>(),
+                                                                             prec == BSM_BF16);
+        }
+    }
+    k_zero_counters<<<1, 64, 0, st>>>(cfg.queues, counters.as<unsigned>());
+    const int blocks = kCUs * cfg.waves_per_cu / 4;
+    k_product_batch<<<blocks, 256, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(), cfg.queues,
+                                            counters.as<unsigned>(), c->zero_block.as<double>());
+    BSM_HIP_TRY(hipGetLastError());
+}
+
+#define BATCH_BEGIN try {
+#define BATCH_END                                                     \
+    }                                                                 \
+    catch (const Error &e) { return fail(e.code, e.msg); }            \
+    catch (...) { return fail(BSM_EINVAL, "unknown error"); }
+
+extern "C" {
+
+int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *B, const bsm_matrix *C,
+                     const double *alpha, const double *beta, int precision, bsm_batch *out)
+{
+    BATCH_BEGIN
+    BSM_REQUIRE(ctx && A && B && C && alpha && beta && out, BSM_EINVAL, "NULL argument");
+    BSM_REQUIRE(n >= 1, BSM_EINVAL, "empty batch");
+    BSM_REQUIRE(precision == BSM_F64 || precision == BSM_F32 || precision == BSM_BF16, BSM_EINVAL,
+                "bad precision");
+    std::unique_ptr<bsm_batch_s> bt(new bsm_batch_s());
+    Context *c = &ctx->c;
+    bt->c = c;
+    bt->n = n;
+    bt->prec = precision;
+    std::vector<BatchDesc> d(n);
+    for (int p = 0; p < n; ++p) {
+        check_matrix(&A[p], "A");
+        check_matrix(&B[p], "B");
+        check_matrix(&C[p], "C");
+        check_same_shape(&A[p], &B[p]);
+        check_same_shape(&A[p], &C[p]);
+        const int b = C[p].pattern->b;
+        BSM_REQUIRE(b == 4 || b == 9, BSM_EINVAL, "batched products support b = 4 and 9");
+        Plan *plan = get_plan(c, A[p].pattern, B[p].pattern, C[p].pattern);
+        BSM_REQUIRE(plan->G == 4, BSM_EINVAL, "batched products need plans with 4 rows per wave");
+        bt->plans.push_back(plan);
+        bt->pa.push_back(A[p].pattern);
+        bt->pb.push_back(B[p].pattern);
+        bt->pc.push_back(C[p].pattern);
+        bt->A.push_back((const double *)A[p].blocks);
+        bt->B.push_back((const double *)B[p].blocks);
+        bt->C.push_back((double *)C[p].blocks);
+        bt->a_n.push_back(nelems(A[p].pattern));
+        bt->b_n.push_back(nelems(B[p].pattern));
+        bt->flops += plan->flops;
+        bt->ntiles += plan->ntiles;
+        // per-tile entry counts: the schedule's weights
+        std::vector<int64_t> eb((size_t)plan->ntiles + 1);
+        BSM_HIP_TRY(hipMemcpy(eb.data(), plan->ebeg.ptr, sizeof(int64_t) * eb.size(), hipMemcpyDeviceToHost));
+        std::vector<int64_t> w((size_t)plan->ntiles);
+        for (int64_t t = 0; t < plan->ntiles; ++t) w[t] = eb[t + 1] - eb[t];
+        bt->work.push_back(std::move(w));
+        BatchDesc &x = d[p];
+        x.hdr = plan->hdr.as<int>();
+        x.ebeg = plan->ebeg.as<int64_t>();
+        x.ent = plan->ent.as<int>();
+        x.C = (double *)C[p].blocks;
+        x.alpha = alpha[p];
+        x.beta = beta[p];
+        if (precision == BSM_F64) {
+            x.kind = b == 9 ? kKindF64Dpp9 : kKindF64Dpp4;
+            x.A = A[p].blocks;
+            x.B = B[p].blocks;
+        } else {
+            x.kind = b == 9 ? kKindF32b9 : kKindF32b4;
+            bt->a32.emplace_back(c, sizeof(float) * (size_t)std::max<int64_t>(1, bt->a_n.back()));
+            bt->b32.emplace_back(c, sizeof(float) * (size_t)std::max<int64_t>(1, bt->b_n.back()));
+            x.A = bt->a32.back().ptr;
+            x.B = bt->b32.back().ptr;
+        }
+    }
+    bt->desc = DevBuf(c, sizeof(BatchDesc) * n);
+    BSM_HIP_TRY(hipMemcpy(bt->desc.ptr, d.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice));
+    bt->counters = DevBuf(c, sizeof(unsigned) * 64);
+    bt->best = bsm_batch_config{BSM_ORDER_HEAVY_FIRST, 8, 1};
+    *out = bt.release();
+    return BSM_OK;
+    BATCH_END
+}
+
+int bsm_batch_run(bsm_batch bt, const bsm_batch_config *cfg)
+{
+    BATCH_BEGIN
+    BSM_REQUIRE(bt != nullptr, BSM_EINVAL, "batch is NULL");
+    bt->run(cfg ? *cfg : bt->best);
+    return BSM_OK;
+    BATCH_END
+}
+
+int bsm_batch_flops(bsm_batch bt, double *flops)
+{
+    BATCH_BEGIN
+    BSM_REQUIRE(bt && flops, BSM_EINVAL, "NULL argument");
+    *flops = bt->flops;
+    return BSM_OK;
+    BATCH_END
+}
+
+int bsm_batch_tune(bsm_batch bt, int reps, bsm_batch_config *best, double *best_ms)
+{
+    BATCH_BEGIN
+    BSM_REQUIRE(bt != nullptr && reps >= 1, BSM_EINVAL, "bad argument");
+    hipStream_t st = bt->c->stream;
+    hipEvent_t e0, e1;
+    BSM_HIP_TRY(hipEventCreate(&e0));
+    BSM_HIP_TRY(hipEventCreate(&e1));
+    double best_t = INFINITY;
+    bsm_batch_config arg{};
+    const int orders[3] = {BSM_ORDER_HEAVY_FIRST, BSM_ORDER_BY_PRODUCT, BSM_ORDER_INTERLEAVE};
+    const int waves[3] = {4, 8, 16};
+    const int queues[2] = {1, 8};
+    for (int o : orders)
+        for (int q : queues)
+            for (int w : waves) {
+                bsm_batch_config cfg{o, w, q};
+                bt->run(cfg);   // also builds the schedule outside the timing
+                BSM_HIP_TRY(hipEventRecord(e0, st));
+                for (int r = 0; r < reps; ++r) bt->run(cfg);
+                BSM_HIP_TRY(hipEventRecord(e1, st));
+                BSM_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                BSM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms / reps < best_t) {
+                    best_t = ms / reps;
+                    arg = cfg;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    bt->best = arg;
+    bt->tuned = true;
+    if (best) *best = arg;
+    if (best_ms) *best_ms = best_t;
+    return BSM_OK;
+    BATCH_END
+}
+
+int bsm_batch_destroy(bsm_batch bt)
+{
+    if (bt) {
+        (void)hipStreamSynchronize(bt->c->stream);
+        delete bt;
+    }
+    return BSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,315 @@
+// Device code of one product tile (one wavefront), shared by the per-product
+// kernels and the persistent batch kernel.  See product.hip for the plan layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+namespace bsm {
+
+// Wave-uniform read-only view: loads through it become scalar loads when the
+// address is uniform.
+template <class T> using const_as4 = const __attribute__((address_space(4))) T;
+
+template <int B, int G, class T>
+__device__ inline void multiply_entry(const_as4<int> *entu, int64_t q, const_as4<T> *vAu, const T (&bv)[B],
+                                      bool bact, const bool (&cact)[G], T (&acc)[G][B])
+{
+    constexpr int BB = B * B;
+    constexpr int ES = G + 64 / B;
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        const int as = entu[q * ES + a];
+        if (as < 0) continue;
+        if (bact && cact[a]) {
+            const_as4<T> *ap = vAu + (int64_t)as * BB;
+#pragma unroll
+            for (int r = 0; r < B; ++r)
+#pragma unroll
+                for (int m = 0; m < B; ++m) acc[a][r] = fma(ap[r * B + m], bv[m], acc[a][r]);
+        }
+    }
+}
+
+// Tile header, ints: rows[G] (atom ids, -1 = padding), cslot[G][JT] (slot of
+// (i_a, j) in C or -1).  Entries of tile t: ebeg[t] .. ebeg[t+1] (an even count;
+// an odd list ends in a padding entry whose A slots are all -1), each G + JT
+// ints: aslot[G] (slot of (i_a, k) in A or -1), bslot[JT] (slot of (k, j) in B
+// or -1).  The entry array has 4 spare entries at its end, so the index
+// prefetch past a tile's last entry stays in bounds.
+// T = double: FP64 product.  T = float: operands already rounded to FP32 (or to
+// BF16 and stored as FP32), FP32 fused multiply-add accumulation in the same
+// (k, m) order, the FP32 sums widened to FP64 for alpha, beta and the store.
+template <int B, int G, class T>
+__device__ inline void tile_sgpr(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
+                                 const int *__restrict__ ent, const T *__restrict__ vA, const T *__restrict__ vB,
+                                 double *__restrict__ vC, double alpha, double beta)
+{
+    constexpr int JT = 64 / B;
+    constexpr int BB = B * B;
+    constexpr int HS = G + G * JT;
+    constexpr int ES = G + JT;
+    const int lane = threadIdx.x & 63;
+    const int jl0 = lane / B, c = lane - jl0 * B;
+    const bool lane_ok = jl0 < JT;
+    const int jl = lane_ok ? jl0 : JT - 1;     // spare lanes read a valid column and stay masked
+    const int *h = hdr + tile * HS;
+    int cs[G];
+    bool cact[G];
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        cs[a] = lane_ok ? h[G + a * JT + jl] : -1;
+        cact[a] = cs[a] >= 0;
+    }
+    T acc[G][B];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int r = 0; r < B; ++r) acc[a][r] = T(0);
+
+    const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
+    const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
+    const int n = (int)(e1 - e0);                  // even
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
+    const int *entv = ent + e0 * ES + G + jl;      // this lane's B slot column
+    const_as4<T> *vAu = (const_as4<T> *)vA;
+    const T *vBc = vB + c;
+
+    // ping-pong buffers: entry q in ba while q+1 loads into bb, then q+1 in bb
+    // while q+2 loads into ba; B slot indices run two entries ahead.
+    T ba[B], bb[B];
+    int ia = entv[0], ib = entv[ES];
+    ia = (0 < n) ? ia : -1;
+    ib = (1 < n) ? ib : -1;
+    {
+        const T *bp = vBc + (int64_t)max(ia, 0) * BB;
+#pragma unroll
+        for (int m = 0; m < B; ++m) ba[m] = bp[m * B];
+    }
+    for (int q = 0; q < n; q += 2) {
+        int ic = entv[(int64_t)(q + 2) * ES];
+        ic = (q + 2 < n) ? ic : -1;
+        {
+            const T *bp = vBc + (int64_t)max(ib, 0) * BB;
+#pragma unroll
+            for (int m = 0; m < B; ++m) bb[m] = bp[m * B];
+        }
+        multiply_entry<B, G, T>(entu, q, vAu, ba, ia >= 0, cact, acc);
+        int id = entv[(int64_t)(q + 3) * ES];
+        id = (q + 3 < n) ? id : -1;
+        {
+            const T *bp = vBc + (int64_t)max(ic, 0) * BB;
+#pragma unroll
+            for (int m = 0; m < B; ++m) ba[m] = bp[m * B];
+        }
+        multiply_entry<B, G, T>(entu, q + 1, vAu, bb, ib >= 0, cact, acc);
+        ia = ic;
+        ib = id;
+    }
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (!cact[a]) continue;
+        double *cp = vC + (int64_t)cs[a] * BB + c;
+        if (beta == 0.0) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r] + beta * cp[r * B];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- DPP variant
+// The same tiles and entry lists, with the uniform operand A_{i_a k} held in
+// VGPRs instead of SGPRs: lane l of every row of 16 lanes holds elements
+// l % 16 + 16 v (v < NA) of the block, loaded with ordinary pipelined vector
+// loads, and each FMA takes its A element by a DPP row broadcast
+// (row_newbcast: lane n of each 16-lane row to the whole row).  This removes
+// the scalar-load round trips of the SGPR variant from the inner loop.
+// One output row r of a block product: acc += sum_m A[r][m] * b[m], A[r][m]
+// broadcast from lane (r*b + m) % 16 of register (r*b + m) / 16.  The row's
+// FMAs form one asm block that starts with two wait states: a VALU write of a
+// register followed by a DPP read of it needs them, and the compiler does not
+// track that hazard into inline asm.
+#define BSM_FMA_DPP(acc, a, bq, lane) "v_fmac_f64_dpp " acc ", " a ", " bq " row_newbcast:" lane " row_mask:0xf bank_mask:0xf\n"
+
+template <int B, int NA, int R> struct DppRow;
+
+template <int NA, int R> struct DppRow<9, NA, R> {
+    static constexpr int e(int m) { return R * 9 + m; }
+    __device__ static inline void run(double &acc, const double (&av)[NA], const double (&bv)[9])
+    {
+        asm("s_nop 1\n"
+            BSM_FMA_DPP("%0", "%1", "%10", "%19") BSM_FMA_DPP("%0", "%2", "%11", "%20")
+            BSM_FMA_DPP("%0", "%3", "%12", "%21") BSM_FMA_DPP("%0", "%4", "%13", "%22")
+            BSM_FMA_DPP("%0", "%5", "%14", "%23") BSM_FMA_DPP("%0", "%6", "%15", "%24")
+            BSM_FMA_DPP("%0", "%7", "%16", "%25") BSM_FMA_DPP("%0", "%8", "%17", "%26")
+            BSM_FMA_DPP("%0", "%9", "%18", "%27")
+            : "+v"(acc)
+            : "v"(av[e(0) >> 4]), "v"(av[e(1) >> 4]), "v"(av[e(2) >> 4]), "v"(av[e(3) >> 4]),
+              "v"(av[e(4) >> 4]), "v"(av[e(5) >> 4]), "v"(av[e(6) >> 4]), "v"(av[e(7) >> 4]),
+              "v"(av[e(8) >> 4]),
+              "v"(bv[0]), "v"(bv[1]), "v"(bv[2]), "v"(bv[3]), "v"(bv[4]), "v"(bv[5]), "v"(bv[6]), "v"(bv[7]),
+              "v"(bv[8]),
+              "n"(e(0) & 15), "n"(e(1) & 15), "n"(e(2) & 15), "n"(e(3) & 15), "n"(e(4) & 15), "n"(e(5) & 15),
+              "n"(e(6) & 15), "n"(e(7) & 15), "n"(e(8) & 15));
+    }
+};
+
+template <int NA, int R> struct DppRow<4, NA, R> {
+    static constexpr int e(int m) { return R * 4 + m; }
+    __device__ static inline void run(double &acc, const double (&av)[NA], const double (&bv)[4])
+    {
+        asm("s_nop 1\n"
+            BSM_FMA_DPP("%0", "%1", "%5", "%9") BSM_FMA_DPP("%0", "%2", "%6", "%10")
+            BSM_FMA_DPP("%0", "%3", "%7", "%11") BSM_FMA_DPP("%0", "%4", "%8", "%12")
+            : "+v"(acc)
+            : "v"(av[e(0) >> 4]), "v"(av[e(1) >> 4]), "v"(av[e(2) >> 4]), "v"(av[e(3) >> 4]),
+              "v"(bv[0]), "v"(bv[1]), "v"(bv[2]), "v"(bv[3]),
+              "n"(e(0) & 15), "n"(e(1) & 15), "n"(e(2) & 15), "n"(e(3) & 15));
+    }
+};
+#undef BSM_FMA_DPP
+
+template <int B, int NA, int... R>
+__device__ inline void fma_block(double (&acc)[B], const double (&av)[NA], const double (&bv)[B],
+                                 std::integer_sequence<int, R...>)
+{
+    (DppRow<B, NA, R>::run(acc[R], av, bv), ...);
+}
+
+// Element l16 + 16 v of the block into register v; indices past the block wrap
+// to its start (unused lanes, kept lane-varying so every element arrives by a
+// vector load straight into its VGPR).
+template <int B, int NA>
+__device__ inline void load_a(double (&av)[NA], const double *__restrict__ vA, int slot, int l16)
+{
+    constexpr int BB = B * B;
+    const double *ap = vA + (int64_t)max(slot, 0) * BB;
+#pragma unroll
+    for (int v = 0; v < NA; ++v) {
+        int idx = l16 + 16 * v;
+        if (idx >= BB) idx -= BB;
+        av[v] = ap[idx];
+    }
+}
+
+// Lanes whose (k, j) block is absent read a block of zeros instead: the DPP
+// broadcast needs every lane of the wave active (a read from an exec-disabled
+// source lane is invalid), so absent triples are multiplied by zero rather than
+// masked off.
+template <int B>
+__device__ inline void load_b(double (&bv)[B], const double *__restrict__ vBc, const double *__restrict__ zc, int slot)
+{
+    const double *bp = (slot >= 0) ? vBc + (int64_t)slot * (B * B) : zc;
+#pragma unroll
+    for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
+}
+
+template <int B, int G, int NA>
+__device__ inline void dpp_entry(const int (&as)[G], const double (&av)[G][NA], const double (&bv)[B],
+                                 double (&acc)[G][B])
+{
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (as[a] < 0) continue;   // wave-uniform
+        fma_block<B, NA>(acc[a], av[a], bv, std::make_integer_sequence<int, B>{});
+    }
+}
+
+template <int B, int G>
+__device__ inline void tile_dpp(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
+                                const int *__restrict__ ent, const double *__restrict__ vA,
+                                const double *__restrict__ vB, const double *__restrict__ zblk,
+                                double *__restrict__ vC, double alpha, double beta)
+{
+    constexpr int JT = 64 / B;
+    constexpr int BB = B * B;
+    constexpr int NA = (BB + 15) / 16;
+    constexpr int HS = G + G * JT;
+    constexpr int ES = G + JT;
+    const int lane = threadIdx.x & 63;
+    const int l16 = lane & 15;
+    const int jl0 = lane / B, c = lane - jl0 * B;
+    const bool lane_ok = jl0 < JT;
+    const int jl = lane_ok ? jl0 : JT - 1;
+    const int *h = hdr + tile * HS;
+    int cs[G];
+    bool cact[G];
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        cs[a] = lane_ok ? h[G + a * JT + jl] : -1;
+        cact[a] = cs[a] >= 0;
+    }
+    double acc[G][B];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int r = 0; r < B; ++r) acc[a][r] = 0.0;
+
+    const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
+    const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
+    const int n = (int)(e1 - e0);                  // even
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
+    const int *entv = ent + e0 * ES + G + jl;
+    const double *vBc = vB + c;
+    const double *zc = zblk + c;
+
+    // ping-pong: entry q in (xa, ba) while q+1 loads into (xb, bb), and so on;
+    // B slot indices two entries ahead, A slots are wave-uniform scalar loads.
+    double xa[G][NA], xb[G][NA], ba[B], bb[B];
+    int asa[G], asb[G];
+    int ia = entv[0], ib = entv[ES];
+    ia = (0 < n) ? ia : -1;
+    ib = (1 < n) ? ib : -1;
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        asa[a] = (0 < n) ? entu[a] : -1;
+        load_a<B, NA>(xa[a], vA, asa[a], l16);
+    }
+    load_b<B>(ba, vBc, zc, ia);
+    for (int q = 0; q < n; q += 2) {
+        int ic = entv[(int64_t)(q + 2) * ES];
+        ic = (q + 2 < n) ? ic : -1;
+#pragma unroll
+        for (int a = 0; a < G; ++a) {
+            asb[a] = entu[(int64_t)(q + 1) * ES + a];
+            load_a<B, NA>(xb[a], vA, asb[a], l16);
+        }
+        load_b<B>(bb, vBc, zc, ib);
+        dpp_entry<B, G, NA>(asa, xa, ba, acc);
+        int id = entv[(int64_t)(q + 3) * ES];
+        id = (q + 3 < n) ? id : -1;
+#pragma unroll
+        for (int a = 0; a < G; ++a) {
+            asa[a] = (q + 2 < n) ? entu[(int64_t)(q + 2) * ES + a] : -1;
+            load_a<B, NA>(xa[a], vA, asa[a], l16);
+        }
+        load_b<B>(ba, vBc, zc, ic);
+        dpp_entry<B, G, NA>(asb, xb, bb, acc);
+        ia = ic;
+        ib = id;
+    }
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (!cact[a]) continue;
+        double *cp = vC + (int64_t)cs[a] * BB + c;
+        if (beta == 0.0) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
+        }
+    }
+}
+
+
+}  // namespace bsm

@@ -286,3 +286,20 @@ def random_blocks(nnz: int, b: int, seed: int, stream: int = 7, scale: float = 1
     """Seeded uniform[-scale, scale] blocks, for feeding kernels arbitrary operands."""
     u = counter_uniform(seed, stream, np.arange(nnz * b * b))
     return (scale * (2.0 * u - 1.0)).reshape(nnz, b, b)
+
+
+def batch_cells(count: int = 64, seed: int = 2205, lo: int = 512, hi: int = 4096, min_cells: int = 4):
+    """Cell counts and orbitals per atom of a batch of uneven systems.
+
+    Target sizes uniform in [lo, hi] atoms, b = 4 or 9 by a seeded coin; each
+    system is the orthorhombic n1 x n2 x n3 block of conventional cells (every
+    n_i >= min_cells) whose 8 n1 n2 n3 atoms are closest to its target.
+    """
+    shapes = [(a, b, c) for a in range(min_cells, 17) for b in range(a, 17) for c in range(b, 17)]
+    out = []
+    for k in range(count):
+        target = lo + (hi - lo) * float(counter_uniform(seed, 11, k))
+        orb = 9 if counter_uniform(seed, 12, k) >= 0.5 else 4
+        best = min(shapes, key=lambda s: (abs(8 * s[0] * s[1] * s[2] - target), s))
+        out.append((best, orb))
+    return out

@@ -412,3 +412,47 @@ def test_mixed_schedule_reaches_fp64_energy(bsm, ctx, b):
     assert abs(rg["E"] - E_ref) / 64 < 1e-6 and abs(ro["E"] - E_ref) / 64 < 1e-6
     assert abs(rg["E"] - ro["E"]) / 64 < 1e-6
     assert rg["product_flops"] > 0
+
+
+# ------------------------------------------------------------------ batched persistent launch
+def _batch_case(bsm, ctx, seed):
+    """Uneven small systems, b = 4 and 9, three product shapes."""
+    specs = [((2, 2, 2), 4), ((2, 2, 3), 9), ((2, 3, 3), 4), ((3, 3, 3), 9), ((2, 2, 2), 9), ((2, 3, 2), 4)]
+    out = []
+    for n, (cells, b) in enumerate(specs):
+        pos, box, _ = synth.diamond_positions(cells)
+        ra, rb, rc = [(6, 8, 14), (8, 8, 8), (14, 6, 10)][n % 3]
+        gp = {r: gpat(bsm, ctx, pos, box, float(r), b) for r in {ra, rb, rc}}
+        op = {r: O.create_pattern(pos, box, float(r)) for r in {ra, rb, rc}}
+        a = synth.random_blocks(op[ra].nnz, b, seed + 3 * n)
+        bb = synth.random_blocks(op[rb].nnz, b, seed + 3 * n + 1)
+        out.append(dict(b=b, A=gmat(bsm, gp[ra], a), B=gmat(bsm, gp[rb], bb), C=bsm.Matrix(gp[rc]),
+                        C1=bsm.Matrix(gp[rc]), oA=O.Matrix(op[ra], b, a), oB=O.Matrix(op[rb], b, bb), oPC=op[rc]))
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_equals_separate_products(bsm, ctx, prec):
+    case = _batch_case(bsm, ctx, 100 + prec)
+    say(f"batch prec={prec}: {len(case)} products")
+    batch = bsm.Batch(ctx, [(c["A"], c["B"], c["C"]) for c in case], alpha=1.5, beta=0.0, precision=prec)
+    for order in (0, 1, 2):
+        for queues in (1, 8):
+            for c in case:
+                c["C"].blocks.fill_(float("nan"))
+            batch.run(order=order, waves_per_cu=8, queues=queues)
+            for c in case:
+                bsm.multiply_truncate_prec(prec, 1.5, c["A"], c["B"], 0.0, c["C1"])
+                assert torch.equal(c["C"].blocks, c["C1"].blocks), (order, queues, c["b"])
+    for c in case:
+        Co = O.Matrix(c["oPC"], c["b"])
+        O.multiply_truncate_mixed(prec, 1.5, c["oA"], c["oB"], 0.0, Co)
+        assert rel_err(host(c["C"]), Co.blocks) < 1e-13
+    cfg, ms = batch.tune(reps=1)
+    assert cfg["queues"] in (1, 8) and cfg["waves_per_cu"] in (4, 8, 16) and ms > 0
+    before = [c["C"].blocks.clone() for c in case]
+    batch.run()
+    for c, x in zip(case, before):
+        assert torch.equal(c["C"].blocks, x)
+    assert batch.flops == sum(bsm.product_flops(c["A"].pattern, c["B"].pattern, c["C"].pattern) for c in case)
+    batch.close()
