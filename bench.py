@@ -39,7 +39,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="si4096_b9", choices=["si4096_b9", "si64_b4"])
+    ap.add_argument("--workload", default="si4096_b9", choices=["si4096_b9", "si64_b4", "batch64"],
+                    help="batch64: 64 uneven systems (512-4096 atoms, b = 4 and 9), the 16 A x 16 A -> 16 A "
+                         "product of each, per-product launches against one tuned persistent launch")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--max-lnv", type=int, default=300)
     ap.add_argument("--tol-e", type=float, default=1e-8)
     ap.add_argument("--cpu-rows", type=int, default=1024,
@@ -82,6 +85,98 @@ def product_mode(args):
                       "tflops": flops / (ms * 1e-3) / 1e12, "blocks": P.nnzb,
                       "algorithmic_bytes": 3 * P.nnzb * b * b * 8, "copy_bytes": 2 * src.numel() * 8}),
           flush=True)
+
+
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak
+
+
+def batch_mode(args):
+    """Many independent systems: the dominant product class of each, launched per product and
+    as one persistent launch whose schedule the library's autotuner picks, in FP64 and FP32."""
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    cells = synth.batch_cells(count=args.batch_count)
+    ctx = bsm.Context(0)
+    dev = ctx.device
+    rx = 16.0
+    mats = []
+    t0 = time.perf_counter()
+    for n, (c, b) in enumerate(cells):
+        pos, box, _ = synth.diamond_positions(c)
+        P = bsm.Pattern(ctx, torch.tensor(pos, dtype=torch.float64, device=dev), box, rx, b)
+        g = torch.Generator(device=dev)
+        g.manual_seed(1000 + n)
+        X = bsm.Matrix(P, torch.rand((P.nnzb, b, b), dtype=torch.float64, device=dev, generator=g) - 0.5)
+        mats.append((X, X, bsm.Matrix(P)))
+    torch.cuda.synchronize()
+    natoms = sum(len(synth.diamond_positions(c)[0]) for c, _ in cells)
+    blocks = sum(m[2].pattern.nnzb for m in mats)
+    log(f"[batch] {len(cells)} systems, {natoms} atoms, {blocks} blocks per matrix set, "
+        f"setup {time.perf_counter() - t0:.1f} s, device memory {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
+
+    def checksums():
+        return [float(m[2].blocks.sum()) for m in mats]
+
+    res = {}
+    for prec, name in ((bsm.F64, "f64"), (bsm.F32, "f32")):
+        flops = sum(bsm.product_flops(A.pattern, B.pattern, C.pattern) for A, B, C in mats)
+        for A, B, C in mats:                                    # plans + warm-up
+            bsm.multiply_truncate_prec(prec, 1.0, A, B, 0.0, C)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(args.steps):
+            for A, B, C in mats:
+                bsm.multiply_truncate_prec(prec, 1.0, A, B, 0.0, C)
+        torch.cuda.synchronize()
+        sep_s = (time.perf_counter() - t) / args.steps
+        ref = checksums()
+        log(f"[batch {name}] per-product launches: {sep_s * 1e3:.1f} ms, {flops / sep_s / 1e12:.2f} TFLOP/s")
+        batch = bsm.Batch(ctx, mats, alpha=1.0, beta=0.0, precision=prec)
+        t = time.perf_counter()
+        cfg, tune_ms = batch.tune(reps=1)
+        tune_s = time.perf_counter() - t
+        log(f"[batch {name}] tuned in {tune_s:.1f} s: {cfg}, {tune_ms:.1f} ms")
+        for w in range(args.warmup):
+            batch.run()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream(dev)
+        t = time.perf_counter()
+        ev0.record(stream)
+        for k in range(args.steps):
+            batch.run()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall_s = (time.perf_counter() - t) / args.steps
+        dev_ms = ev0.elapsed_time(ev1) / args.steps
+        same = checksums() == ref
+        log(f"[batch {name}] persistent launch: {dev_ms:.1f} ms, {flops / (dev_ms * 1e-3) / 1e12:.2f} TFLOP/s, "
+            f"matches per-product launches: {same}")
+        res[name] = dict(flops=flops, separate_ms=sep_s * 1e3, batch_ms=dev_ms, wall_s=wall_s, tuned=cfg,
+                         tune_s=tune_s, same=same)
+        batch.close()
+    r64, r32 = res["f64"], res["f32"]
+    achieved = r64["flops"] / (r64["batch_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": "block-sparse GFLOP/s, 64 uneven systems in one persistent launch",
+        "value": round(r64["flops"] / r64["wall_s"] / 1e9, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r64["wall_s"] * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch of {len(cells)} diamond-Si systems, {natoms} atoms, b = 4 and 9, "
+                               f"16 A x 16 A -> 16 A product each", "systems": len(cells), "natoms": natoms,
+                   "b9_systems": sum(1 for _, b in cells if b == 9)},
+        "f64": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r64.items()},
+        "f32": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r32.items()},
+        "f32_gflops": round(r32["flops"] / (r32["batch_ms"] * 1e-3) / 1e9, 2),
+        "batch_speedup_vs_separate_f64": round(r64["separate_ms"] / r64["batch_ms"], 3),
+        "roofline": {"bound": "alu", "kernel": "k_product_batch (FP64)", "achieved": round(achieved, 3),
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": None, "avg_launch_ms": round(r64["batch_ms"], 3)},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(args):
@@ -141,6 +236,9 @@ def main():
         sys.exit(1)
     if args.mode == "product":
         product_mode(args)
+        return
+    if args.workload == "batch64":
+        batch_mode(args)
         return
     s = synth.si4096_b9() if args.workload == "si4096_b9" else synth.si64_b4()
     cut = s.cutoffs

@@ -219,7 +219,8 @@ int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *
 /* Queue the batch on the context stream; cfg NULL = the tuned (or default) schedule. */
 int bsm_batch_run(bsm_batch batch, const bsm_batch_config *cfg);
 /* Time every candidate schedule (3 orders x {1, 8} queues x {4, 8, 16} waves
- * per CU), `reps` runs each, keep the fastest.  Runs the batch many times. */
+ * per CU), `reps` runs each after one shared warm-up run, keep the fastest.
+ * Runs the batch 1 + 18 reps times; synchronises. */
 int bsm_batch_tune(bsm_batch batch, int reps, bsm_batch_config *best, double *best_ms);
 int bsm_batch_flops(bsm_batch batch, double *flops);
 int bsm_batch_destroy(bsm_batch batch);

@@ -319,11 +319,12 @@ int bsm_batch_tune(bsm_batch bt, int reps, bsm_batch_config *best, double *best_
     const int orders[3] = {BSM_ORDER_HEAVY_FIRST, BSM_ORDER_BY_PRODUCT, BSM_ORDER_INTERLEAVE};
     const int waves[3] = {4, 8, 16};
     const int queues[2] = {1, 8};
+    bt->run(bt->best);   // one warm-up (operand pages, caches) for all candidates
     for (int o : orders)
         for (int q : queues)
             for (int w : waves) {
                 bsm_batch_config cfg{o, w, q};
-                bt->run(cfg);   // also builds the schedule outside the timing
+                bt->build_schedule(cfg);   // host work kept out of the timing
                 BSM_HIP_TRY(hipEventRecord(e0, st));
                 for (int r = 0; r < reps; ++r) bt->run(cfg);
                 BSM_HIP_TRY(hipEventRecord(e1, st));

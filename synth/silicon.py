@@ -187,9 +187,39 @@ def _fold(i, j, blocks, natoms):
     return (uk // natoms).astype(np.int32), (uk % natoms).astype(np.int32), summed
 
 
+def _smooth_coefficients(seed, stream, b):
+    """Seeded coefficient tensors of an orbital-pair function of the bond direction.
+
+    U(r)_ab = [C0_ab + C1_abc r_c + C2_abcd r_c r_d] / 4 with C0 symmetric, C1
+    antisymmetric and C2 symmetric in (a, b), so that U(-r) = U(r)^T: the block
+    of the mirrored pair is the transpose, as a symmetric matrix needs.
+    """
+    a = np.arange(b)
+    R0 = 2.0 * counter_uniform(seed, stream, 9000, a[:, None], a[None, :]) - 1.0
+    c = np.arange(3)
+    R1 = 2.0 * counter_uniform(seed, stream, 9001, a[:, None, None], a[None, :, None], c[None, None, :]) - 1.0
+    R2 = 2.0 * counter_uniform(seed, stream, 9002, a[:, None, None, None], a[None, :, None, None],
+                               c[None, None, :, None], c[None, None, None, :]) - 1.0
+    C0 = 0.5 * (R0 + R0.T)
+    C1 = 0.5 * (R1 - R1.transpose(1, 0, 2))
+    C2 = 0.5 * (R2 + R2.transpose(1, 0, 2, 3))
+    C2 = 0.5 * (C2 + C2.transpose(0, 1, 3, 2))
+    return C0, C1, C2
+
+
+def _smooth_blocks(coef, rhat):
+    C0, C1, C2 = coef
+    U = C0[None] + np.einsum("abc,nc->nab", C1, rhat) + np.einsum("abcd,nc,nd->nab", C2, rhat, rhat)
+    return 0.25 * U
+
+
+def _pair_vectors(pos, box, i, j, sh, d):
+    return (pos[j] + sh * box - pos[i]) / d[:, None]
+
+
 def make_system(name: str, ncell, b: int, cutoffs: Dict[str, float], seed: int,
                 displacement_sigma: float = 0.0, s_amp: float = S_AMP,
-                h_random: bool = True) -> SiliconSystem:
+                h_random: bool = True, smooth: bool = False) -> SiliconSystem:
     """Diamond-Si system with seeded S and gapped tight-binding-like H.
 
     S: identity on site; off site exp(-d/1.5 A) * U, U uniform in [-0.3, 0.3],
@@ -202,6 +232,13 @@ def make_system(name: str, ncell, b: int, cutoffs: Dict[str, float], seed: int,
 
     s_amp = 0 gives S = I; h_random = False drops V_rand (both only for tests
     with closed-form answers); a large s_amp makes S indefinite.
+
+    smooth = True makes every block a function of the pair geometry alone, so
+    that S, H (and hence the density matrix) vary smoothly with displacements
+    and can be learned from geometry: the uniform off-site factors become
+    seeded orbital-pair functions of the bond direction (_smooth_coefficients),
+    the on-site part of V_rand is one seeded symmetric block shared by all
+    atoms, and the V_rand scale is fixed on the undisplaced lattice.
     """
     ncell = (ncell,) * 3 if np.isscalar(ncell) else tuple(ncell)
     ideal, box, sub = diamond_positions(ncell)
@@ -223,8 +260,12 @@ def make_system(name: str, ncell, b: int, cutoffs: Dict[str, float], seed: int,
 
     # ---- S -------------------------------------------------------------
     inS = d < rS
-    offS = np.exp(-d[inS] / S_DECAY)[:, None, None] * _pair_random_blocks(
-        seed, STREAM_S, i[inS], j[inS], sh[inS], b, -s_amp, s_amp)
+    if smooth:
+        offS = (s_amp * np.exp(-d[inS] / S_DECAY))[:, None, None] * _smooth_blocks(
+            _smooth_coefficients(seed, STREAM_S, b), _pair_vectors(pos, box, i[inS], j[inS], sh[inS], d[inS]))
+    else:
+        offS = np.exp(-d[inS] / S_DECAY)[:, None, None] * _pair_random_blocks(
+            seed, STREAM_S, i[inS], j[inS], sh[inS], b, -s_amp, s_amp)
     diag = np.arange(natoms)
     eye = np.broadcast_to(np.eye(b), (natoms, b, b))
     S = BlockList(*_fold(np.concatenate([diag, i[inS]]), np.concatenate([diag, j[inS]]),
@@ -232,19 +273,32 @@ def make_system(name: str, ncell, b: int, cutoffs: Dict[str, float], seed: int,
 
     # ---- H -------------------------------------------------------------
     inH = d < rH
-    Vr_off = np.exp(-d[inH] / S_DECAY)[:, None, None] * _pair_random_blocks(
-        seed, STREAM_H, i[inH], j[inH], sh[inH], b, -1.0, 1.0)
-    e = np.arange(b * b)
-    u_on = counter_uniform(seed, STREAM_H, diag[:, None], diag[:, None], 1000, 1000, 1000,
-                           e[None, :]).reshape(natoms, b, b)
-    Von = -1.0 + 2.0 * u_on
-    Von = 0.5 * (Von + np.transpose(Von, (0, 2, 1)))
-    ri, rj, Vr = _fold(np.concatenate([diag, i[inH]]), np.concatenate([diag, j[inH]]),
-                       np.concatenate([Von, Vr_off]), natoms)
+    if smooth:
+        coefH = _smooth_coefficients(seed, STREAM_H, b)
+
+        def vrand(p, ii, jj, ss, dd):
+            off = np.exp(-dd / S_DECAY)[:, None, None] * _smooth_blocks(coefH, _pair_vectors(p, box, ii, jj, ss, dd))
+            on = np.broadcast_to(coefH[0], (natoms, b, b))
+            return _fold(np.concatenate([diag, ii]), np.concatenate([diag, jj]), np.concatenate([on, off]), natoms)
+
+        ri, rj, Vr = vrand(pos, i[inH], j[inH], sh[inH], d[inH])
+        scale_pairs = image_pairs(ideal, box, rH)
+        Ri, Rj, Vi = vrand(ideal, *scale_pairs)
+    else:
+        Vr_off = np.exp(-d[inH] / S_DECAY)[:, None, None] * _pair_random_blocks(
+            seed, STREAM_H, i[inH], j[inH], sh[inH], b, -1.0, 1.0)
+        e = np.arange(b * b)
+        u_on = counter_uniform(seed, STREAM_H, diag[:, None], diag[:, None], 1000, 1000, 1000,
+                               e[None, :]).reshape(natoms, b, b)
+        Von = -1.0 + 2.0 * u_on
+        Von = 0.5 * (Von + np.transpose(Von, (0, 2, 1)))
+        ri, rj, Vr = _fold(np.concatenate([diag, i[inH]]), np.concatenate([diag, j[inH]]),
+                           np.concatenate([Von, Vr_off]), natoms)
+        Ri, Vi = ri, Vr
     rowsum = np.zeros(natoms * b)
-    np.add.at(rowsum, (ri[:, None] * b + np.arange(b)[None, :]).ravel(),
-              np.abs(Vr).sum(axis=2).ravel())
-    Vr *= (0.5 * T_BOND) / rowsum.max() if h_random else 0.0
+    np.add.at(rowsum, (Ri[:, None] * b + np.arange(b)[None, :]).ravel(),
+              np.abs(Vi).sum(axis=2).ravel())
+    Vr = Vr * ((0.5 * T_BOND) / rowsum.max() if h_random else 0.0)
 
     # bonds: topological nearest neighbours of the ideal lattice
     bi, bj, bsh, bd = image_pairs(ideal, box, 0.5 * (2.3513 + 3.8396))
@@ -280,6 +334,13 @@ def si64_b4(seed: int = 2205) -> SiliconSystem:
 def si4096_b9(seed: int = 2205) -> SiliconSystem:
     """4096 atoms (8x8x8 cells, box 43.44 A), 9 orbitals per atom."""
     return make_system("si4096_b9", 8, 9, BIG_CUTOFFS, seed)
+
+
+def displaced_frame(ncell, b: int, seed: int, sigma: float = 0.05, cutoffs=None) -> SiliconSystem:
+    """A geometry-smooth frame: diamond Si with seeded Gaussian displacements of width sigma (A)."""
+    ncell = (ncell,) * 3 if np.isscalar(ncell) else tuple(ncell)
+    return make_system(f"si{8 * ncell[0] * ncell[1] * ncell[2]}_b{b}_frame{seed}", ncell, b,
+                       dict(cutoffs or BIG_CUTOFFS), seed, displacement_sigma=sigma, smooth=True)
 
 
 def random_blocks(nnz: int, b: int, seed: int, stream: int = 7, scale: float = 1.0) -> np.ndarray:
