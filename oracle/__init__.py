@@ -340,9 +340,9 @@ def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: f
     Start Z0 = I / rho with rho the Gershgorin bound of S (so 0 < rho^-1 lambda <= 1).
     T = Z S is kept on P(r_Z + r_S), which holds it exactly, so the residual
     ||I - Z S||_F is exact (summed elementwise over T - I).
-    Stops: residual < tol sqrt(N_b) (tol > 0); max_iter updates; stagnation (the
-    next residual is not smaller: keep the current Z, accepted only when its
-    residual is at most 0.1 sqrt(N_b)); divergence (residual above the first).
+    Stops: residual < tol sqrt(N_b) (tol > 0); max_iter updates; no progress (the
+    next residual is not smaller: keep the current Z, accepted when its residual
+    is at most 0.1 sqrt(N_b), the truncation floor, else divergence).
     """
     nb = S.nrows
     PT = derived_pattern(z_pattern, z_pattern.cutoff + S.pattern.cutoff)
@@ -352,7 +352,7 @@ def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: f
     r = _hotelling_residual(T, nb)
     if not math.isfinite(r):
         return HotellingResult(Z, ENONFINITE, 0, [r], alpha)
-    hist, r0, it, status = [r], r, 0, OK
+    hist, it, status = [r], 0, OK
     while True:
         if tol > 0 and r < tol * math.sqrt(nb):
             status = OK
@@ -367,10 +367,7 @@ def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: f
         if not math.isfinite(rnew):
             status = ENONFINITE
             break
-        if rnew > r0:
-            status = EDIVERGED
-            break
-        if rnew >= r:
+        if rnew >= r:      # no progress: the floor (accept) or divergence
             status = OK if r <= 0.1 * math.sqrt(nb) else EDIVERGED
             break
         Z, T, r = Znew, Tnew, rnew
