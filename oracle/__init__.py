@@ -333,6 +333,9 @@ def _hotelling_residual(T: Matrix, nb: int) -> float:
     return math.sqrt(r2) if math.isfinite(r2) else float("nan")
 
 
+HOTELLING_PROGRESS = 0.99   # an update must cut the residual by at least 1 %
+
+
 def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: float = 1e-12,
                       Z0: Optional[Matrix] = None) -> HotellingResult:
     """Truncated Hotelling iteration Z <- sym(mask_Z(2Z - (Z S) Z)).
@@ -341,8 +344,10 @@ def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: f
     T = Z S is kept on P(r_Z + r_S), which holds it exactly, so the residual
     ||I - Z S||_F is exact (summed elementwise over T - I).
     Stops: residual < tol sqrt(N_b) (tol > 0); max_iter updates; no progress (the
-    next residual is not smaller: keep the current Z, accepted when its residual
-    is at most 0.1 sqrt(N_b), the truncation floor, else divergence).
+    next residual is above 0.99 times the current one: keep the current Z,
+    accepted when its residual is at most 0.1 sqrt(N_b), the truncation floor,
+    else divergence).  Away from the floor an update at least squares the
+    error, so only the floor or divergence stop it this way.
     """
     nb = S.nrows
     PT = derived_pattern(z_pattern, z_pattern.cutoff + S.pattern.cutoff)
@@ -367,7 +372,7 @@ def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: f
         if not math.isfinite(rnew):
             status = ENONFINITE
             break
-        if rnew >= r:      # no progress: the floor (accept) or divergence
+        if rnew >= HOTELLING_PROGRESS * r:   # no real progress: the floor (accept) or divergence
             status = OK if r <= 0.1 * math.sqrt(nb) else EDIVERGED
             break
         Z, T, r = Znew, Tnew, rnew
