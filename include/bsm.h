@@ -240,26 +240,33 @@ typedef struct {
     int max_iter;        /* maximum number of updates */
     double tol;          /* stop when ||I - Z S||_F < tol sqrt(N_b); <= 0: run max_iter */
     int init_given;      /* 0: Z0 = I / rho (rho = largest absolute row sum of S);
-                            1: start from Z's current contents */
+                            1: start from Z's current contents;
+                            2: guarded correction: Z holds dZ; start from
+                               I / rho + dZ when its residual is finite and below
+                               that of I / rho, else from I / rho; a corrected
+                               start that diverges or stops above 0.1 sqrt(N_b)
+                               is rerun from I / rho */
 } hot_params;
 
 typedef struct {
     int status;          /* BSM_OK, BSM_EDIVERGED, BSM_ENOTCONV or BSM_ENONFINITE */
     int iterations;      /* updates accepted */
-    double alpha;        /* 1 / rho of the start */
+    double alpha;        /* 1 / rho (0 when init_given == 1) */
     double *residuals;   /* host, caller-owned, capacity entries (may be NULL) */
     int capacity;
     int n_residuals;     /* residual of Z0 and of every accepted update */
     double product_flops; /* algorithmic flops of the products launched */
+    int start;           /* 0: the iteration ran from I / rho; 1: from Z's contents */
 } hot_result;
 
 /* Truncated Hotelling / Schulz iteration Z <- sym(mask_Z(2Z - (Z S) Z)) on Z's
  * pattern, with T = Z S held exactly on P(r_Z + r_S) and the residual
  * ||I - Z S||_F summed elementwise over T - I (a deterministic reduction).  Stops at
- * the tolerance, at max_iter, or on stagnation (the next residual is not
- * smaller: the current Z is kept; accepted when its residual is at most
- * 0.1 sqrt(N_b), else BSM_EDIVERGED); a residual above the first gives
- * BSM_EDIVERGED.  S and Z must be built from the same positions.  Returns the
+ * the tolerance, at max_iter, or when an update makes no real progress (the
+ * next residual is above 0.99 times the current one: the current Z is kept; accepted when its residual is
+ * at most 0.1 sqrt(N_b), the truncation floor, else BSM_EDIVERGED, which a
+ * growing residual from an indefinite S always gives).  S and Z must be built
+ * from the same positions.  Returns the
  * same code as result->status, except BSM_ENOTCONV, which returns BSM_OK with
  * Z valid. */
 int hotelling_inverse(bsm_ctx ctx, const bsm_matrix *S, const bsm_matrix *Z,

@@ -18,18 +18,23 @@ descriptor of each atom pair.  A network whose last layer is zero therefore
 reproduces the plain starts exactly.
 
 Descriptor of the pair (i, j), r = minimum-image vector from atom i to atom j,
-d = |r|, r_c the cutoff of the pattern it is evaluated on (16 values):
+d = |r|, r_c the cutoff of the pattern it is evaluated on (32 values):
 
     r / r_c (3), d / r_c, (d / r_c)^2, exp(-d / 1.5 A), s_i, s_j,
-    rhat . e_i[a] (a = 0..3), rhat . e_j[a] (a = 0..3)
+    rhat . e_i[a] (a = 0..3), rhat . e_j[a] (a = 0..3),
+    10 (l_i[a] - d0) (a = 0..3), 10 (l_j[a] - d0) (a = 0..3),
+    10 c_i (3), 10 c_j (3), 0, 0
 
-with rhat = r / d (0 on the diagonal).  s_i = +1 or -1 is the sublattice of
-atom i and e_i[a] its bond direction along hybrid a, both read from its four
-nearest neighbours (atom_frames).
+with rhat = r / d (0 on the diagonal), lengths in Angstrom.  s_i = +1 or -1 is
+the sublattice of atom i, e_i[a] and l_i[a] the direction and length of its
+bond along hybrid a, and c_i the mean of the vectors to its four nearest
+neighbours (zero on the ideal lattice), all read from those neighbours
+(atom_frames); d0 = a sqrt(3) / 4 is the ideal bond length, a = 5.43 A.  The
+last two features measure the local strain that displacements cause.
 
 Network (parameters as one flat FP32 array, weights stored input-major):
     h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3,
-    W1: D x H, W2: H x H, W3: H x M, with D = 16, H = width, M = b^2.
+    W1: D x H, W2: H x H, W3: H x M, with D = 32, H = width, M = b^2.
 Loss over a minibatch of n samples: (1 / 2n) sum_s sum_o (y_so - t_so)^2.
 Optimiser: Adam (Kingma and Ba, ICLR 2015, Algorithm 1) with bias correction.
 """
@@ -40,8 +45,9 @@ import dataclasses
 import numpy as np
 
 TETRA = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float) / np.sqrt(3.0)
-DESC_DIM = 16
+DESC_DIM = 32
 DECAY = 1.5   # Angstrom, the decay length of the off-site overlap
+BOND0 = 5.43 * np.sqrt(3.0) / 4.0   # ideal Si-Si bond length, Angstrom
 
 
 def min_image(pos: np.ndarray, box: np.ndarray, i, j) -> np.ndarray:
@@ -50,17 +56,21 @@ def min_image(pos: np.ndarray, box: np.ndarray, i, j) -> np.ndarray:
 
 
 def atom_frames(pos: np.ndarray, box: np.ndarray):
-    """Sublattice sign s (N,) and bond directions e (N, 4, 3) of every atom.
+    """Sublattice sign s (N,), bond directions e (N, 4, 3), bond lengths l (N, 4)
+    and neighbour centroid c (N, 3) of every atom.
 
     The four nearest neighbours are found by brute force over all atoms
     (minimum image), ordered by (squared distance, index).  With v_n their unit
     vectors, s = +1 when sum_n max_a v_n . T_a >= sum_n max_a (-v_n) . T_a, else
-    -1 (T_a: the tetrahedral directions of the first sublattice), and e[a] is
-    the v_n with the largest s v_n . T_a (first such n on ties).
+    -1 (T_a: the tetrahedral directions of the first sublattice), e[a] is
+    the v_n with the largest s v_n . T_a (first such n on ties) and l[a] the
+    length of that neighbour vector; c is the mean of the four neighbour vectors.
     """
     n = len(pos)
     s = np.zeros(n)
     e = np.zeros((n, 4, 3))
+    l = np.zeros((n, 4))
+    c = np.zeros((n, 3))
     for i in range(n):
         others = np.array([j for j in range(n) if j != i])
         v = min_image(pos, box, np.full(len(others), i), others)
@@ -71,14 +81,17 @@ def atom_frames(pos: np.ndarray, box: np.ndarray):
         sA, sB = dots.max(axis=1).sum(), (-dots).max(axis=1).sum()
         s[i] = 1.0 if sA >= sB else -1.0
         for a in range(4):
-            e[i, a] = u[int(np.argmax(s[i] * dots[:, a]))]
-    return s, e
+            q = int(np.argmax(s[i] * dots[:, a]))
+            e[i, a] = u[q]
+            l[i, a] = np.sqrt(d2[order][q])
+        c[i] = v[order].mean(axis=0)
+    return s, e, l, c
 
 
 def pair_descriptors(pos: np.ndarray, box: np.ndarray, rows: np.ndarray, cols: np.ndarray,
                      cutoff: float, frames) -> np.ndarray:
-    """(nnz, 16) descriptors of the pattern slots (rows[k], cols[k]), in slot order."""
-    s, e = frames
+    """(nnz, 32) descriptors of the pattern slots (rows[k], cols[k]), in slot order."""
+    s, e, l, c = frames
     r = min_image(pos, box, rows, cols)
     d = np.sqrt((r * r).sum(1))
     rhat = np.where(d[:, None] > 0, r / np.where(d > 0, d, 1.0)[:, None], 0.0)
@@ -91,6 +104,10 @@ def pair_descriptors(pos: np.ndarray, box: np.ndarray, rows: np.ndarray, cols: n
     out[:, 7] = s[cols]
     out[:, 8:12] = np.einsum("nc,nac->na", rhat, e[rows])
     out[:, 12:16] = np.einsum("nc,nac->na", rhat, e[cols])
+    out[:, 16:20] = 10.0 * (l[rows] - BOND0)
+    out[:, 20:24] = 10.0 * (l[cols] - BOND0)
+    out[:, 24:27] = 10.0 * c[rows]
+    out[:, 27:30] = 10.0 * c[cols]
     return out
 
 

@@ -68,7 +68,25 @@ class _HotParams(ctypes.Structure):
 class _HotResult(ctypes.Structure):
     _fields_ = [("status", c_int), ("iterations", c_int), ("alpha", c_double),
                 ("residuals", ctypes.POINTER(c_double)), ("capacity", c_int), ("n_residuals", c_int),
-                ("product_flops", c_double)]
+                ("product_flops", c_double), ("start", c_int)]
+
+
+class _MlpShape(ctypes.Structure):
+    _fields_ = [("width", c_int), ("out_dim", c_int)]
+
+
+class _Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+class _TrainParams(ctypes.Structure):
+    _fields_ = [("epochs", c_int), ("batch", c_int), ("opt", _Adam)]
+
+
+class _GuessResult(ctypes.Structure):
+    _fields_ = [("accepted", c_int), ("E_plain", c_double), ("N_plain", c_double), ("E_guess", c_double),
+                ("N_guess", c_double), ("product_flops", c_double)]
 
 
 class _ProductStat(ctypes.Structure):
@@ -146,6 +164,22 @@ EXPORTS = {
     "lnv_state_reset": (c_int, [c_void_p, ctypes.POINTER(_LNVParams), ctypes.POINTER(c_double)]),
     "lnv_solve": (c_int, [c_void_p, ctypes.POINTER(_LNVSchedule), ctypes.POINTER(_LNVSolveResult)]),
     "lnv_idempotency_error": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
+    # learned initial guess (include/bsm_guess.h)
+    "bsm_mlp_param_count": (c_int64, [ctypes.POINTER(_MlpShape)]),
+    "bsm_mlp_create": (c_int, [c_void_p, ctypes.POINTER(_MlpShape), c_void_p, ctypes.POINTER(c_void_p)]),
+    "bsm_mlp_get_params": (c_int, [c_void_p, c_void_p]),
+    "bsm_mlp_set_params": (c_int, [c_void_p, c_void_p]),
+    "bsm_mlp_destroy": (c_int, [c_void_p]),
+    "bsm_pair_descriptors": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "bsm_mlp_forward": (c_int, [c_void_p, c_int, c_int64, c_void_p, c_void_p]),
+    "bsm_mlp_loss_grad": (c_int, [c_void_p, c_int64, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]),
+    "bsm_mlp_adam_step": (c_int, [c_void_p, ctypes.POINTER(_Adam), c_void_p]),
+    "bsm_mlp_train": (c_int, [c_void_p, ctypes.POINTER(_TrainParams), c_int64, c_void_p, c_void_p, c_void_p,
+                              ctypes.POINTER(c_double)]),
+    "bsm_mlp_targets": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix), c_double, c_void_p]),
+    "bsm_mlp_predict_blocks": (c_int, [c_void_p, c_int, c_void_p, c_double, c_double, ctypes.POINTER(_Matrix)]),
+    "lnv_state_reset_guess": (c_int, [c_void_p, ctypes.POINTER(_LNVParams), ctypes.POINTER(_Matrix), c_double,
+                                      ctypes.POINTER(_GuessResult)]),
 }
 
 
@@ -244,7 +278,7 @@ class Context:
 
     def close(self):
         # solver states and batches before the patterns they point into
-        for ch in sorted(self._children, key=lambda o: not isinstance(o, (LNV, Batch))):
+        for ch in sorted(self._children, key=lambda o: not isinstance(o, (LNV, Batch, MLP))):
             ch.close()
         if self.handle:
             _lib.bsm_ctx_destroy(self.handle)
@@ -411,19 +445,25 @@ class HotellingResult:
     alpha: float
     residuals: List[float]
     product_flops: float = 0.0
+    start: int = 0
+
+
+INIT_PLAIN, INIT_GIVEN, INIT_GUARDED = 0, 1, 2
 
 
 def hotelling_inverse(S: Matrix, Z: Matrix, max_iter: int = 100, tol: float = 1e-12,
-                      init_given: bool = False, raise_on_error: bool = True) -> HotellingResult:
-    cap = max_iter + 2
+                      init_given: int = INIT_PLAIN, raise_on_error: bool = True) -> HotellingResult:
+    """init_given: INIT_PLAIN (I / rho), INIT_GIVEN (Z's contents) or INIT_GUARDED (Z's contents
+    when they start closer to S^-1, with I / rho as fallback); True / False mean GIVEN / PLAIN."""
+    cap = 2 * max_iter + 4
     buf = (c_double * cap)()
-    prm = _HotParams(int(max_iter), float(tol), int(bool(init_given)))
-    res = _HotResult(0, 0, 0.0, ctypes.cast(buf, ctypes.POINTER(c_double)), cap, 0, 0.0)
+    prm = _HotParams(int(max_iter), float(tol), int(init_given))
+    res = _HotResult(0, 0, 0.0, ctypes.cast(buf, ctypes.POINTER(c_double)), cap, 0, 0.0, 0)
     code = _lib.hotelling_inverse(Z.pattern.ctx.handle, S.c, Z.c, ctypes.byref(prm), ctypes.byref(res))
     if code != OK and raise_on_error:
         _check(code)
     return HotellingResult(res.status, res.iterations, res.alpha, list(buf[: min(res.n_residuals, cap)]),
-                           res.product_flops)
+                           res.product_flops, res.start)
 
 
 @dataclass
@@ -474,6 +514,17 @@ class LNV:
         return LNVResult(r.E, r.Omega, r.N, r.mu, r.alpha, r.beta, r.dE, tuple(r.c), bool(r.converged),
                          r.status, r.product_flops)
 
+    def reset_guess(self, dL: Matrix, n_tol: float = 0.01, precision: Optional[int] = None) -> dict:
+        """Restart from c mask_L(Z) + dL when that start is better (lower E, N within n_tol N_e),
+        else from c mask_L(Z)."""
+        if precision is not None:
+            self.precision = int(precision)
+        prm = _LNVParams(self.n_electrons, self.mode, self.mu, self.tol_E, 1, self.precision)
+        r = _GuessResult()
+        _check(_lib.lnv_state_reset_guess(self.handle, ctypes.byref(prm), dL.c, float(n_tol), ctypes.byref(r)))
+        return dict(accepted=bool(r.accepted), E_plain=r.E_plain, N_plain=r.N_plain, E_guess=r.E_guess,
+                    N_guess=r.N_guess, product_flops=r.product_flops)
+
     def idempotency_error(self) -> float:
         """||mask(KS KS) - KS||_F / ||KS||_F of the current L (FP64)."""
         e = c_double()
@@ -494,6 +545,106 @@ class LNV:
     def close(self):
         if getattr(self, "handle", None) and self.ctx.handle:
             _lib.lnv_state_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
+
+
+# --------------------------------------------------------------------------- learned initial guess
+
+DESC_DIM, MLP_WIDTH = 32, 128
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def pair_descriptors(neighbours: Pattern, P: Pattern) -> torch.Tensor:
+    """(nnzb(P), 16) FP32 descriptors of P's slots; frames from the four nearest atoms in `neighbours`."""
+    X = torch.empty((max(P.nnzb, 1), DESC_DIM), dtype=torch.float32, device=P.ctx.device)
+    _check(_lib.bsm_pair_descriptors(P.ctx.handle, neighbours.handle, P.handle, _ptr(X)))
+    return X[: P.nnzb]
+
+
+def mlp_targets(A: Matrix, B: Matrix, scale: float) -> torch.Tensor:
+    """(nnzb, b^2) FP32 training targets (A - B) / scale."""
+    P = A.pattern
+    T = torch.empty((max(P.nnzb, 1), P.b * P.b), dtype=torch.float32, device=P.ctx.device)
+    _check(_lib.bsm_mlp_targets(P.ctx.handle, A.c, B.c, float(scale), _ptr(T)))
+    return T[: P.nnzb]
+
+
+def mlp_param_count(out_dim: int, width: int = MLP_WIDTH) -> int:
+    n = _lib.bsm_mlp_param_count(ctypes.byref(_MlpShape(int(width), int(out_dim))))
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+class MLP:
+    """Three-layer perceptron on the GPU (parameters FP32; the caller supplies the initial values)."""
+
+    def __init__(self, ctx: Context, out_dim: int, params, width: int = MLP_WIDTH):
+        self.ctx, self.out_dim, self.width = ctx, int(out_dim), int(width)
+        self.count = mlp_param_count(out_dim, width)
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.shape == (self.count,), (p.shape, self.count)
+        h = c_void_p()
+        _check(_lib.bsm_mlp_create(ctx.handle, ctypes.byref(_MlpShape(self.width, self.out_dim)),
+                                   p.ctypes.data_as(c_void_p), ctypes.byref(h)))
+        self.handle = h
+        ctx._children.add(self)
+
+    @property
+    def params(self) -> np.ndarray:
+        p = np.empty(self.count, np.float32)
+        _check(_lib.bsm_mlp_get_params(self.handle, p.ctypes.data_as(c_void_p)))
+        return p
+
+    @params.setter
+    def params(self, values) -> None:
+        p = np.ascontiguousarray(values, np.float32)
+        assert p.shape == (self.count,)
+        _check(_lib.bsm_mlp_set_params(self.handle, p.ctypes.data_as(c_void_p)))
+
+    def forward(self, X: torch.Tensor, precision: int = F32) -> torch.Tensor:
+        X = X.contiguous()
+        Y = torch.empty((max(X.shape[0], 1), self.out_dim), dtype=torch.float32, device=X.device)
+        _check(_lib.bsm_mlp_forward(self.handle, int(precision), X.shape[0], _ptr(X), _ptr(Y)))
+        return Y[: X.shape[0]]
+
+    def loss_grad(self, X: torch.Tensor, T: torch.Tensor):
+        g = torch.empty(self.count, dtype=torch.float32, device=X.device)
+        loss = c_double()
+        _check(_lib.bsm_mlp_loss_grad(self.handle, X.shape[0], _ptr(X.contiguous()), _ptr(T.contiguous()),
+                                      ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def adam_step(self, grad: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
+        _check(_lib.bsm_mlp_adam_step(self.handle, ctypes.byref(_Adam(lr, beta1, beta2, eps)), _ptr(grad)))
+
+    def train(self, X: torch.Tensor, T: torch.Tensor, epochs: int, batch: int, lr=1e-3, beta1=0.9,
+              beta2=0.999, eps=1e-8, perm: Optional[torch.Tensor] = None) -> List[float]:
+        """Minibatch Adam; perm (int32 device tensor) orders the samples.  Returns per-epoch mean losses."""
+        losses = (c_double * max(int(epochs), 1))()
+        prm = _TrainParams(int(epochs), int(batch), _Adam(lr, beta1, beta2, eps))
+        if perm is not None:
+            assert perm.dtype == torch.int32 and perm.numel() == X.shape[0]
+        _check(_lib.bsm_mlp_train(self.handle, ctypes.byref(prm), X.shape[0], _ptr(X.contiguous()),
+                                  _ptr(T.contiguous()), _ptr(perm), losses))
+        return list(losses[: int(epochs)])
+
+    def predict_blocks(self, X: torch.Tensor, M: Matrix, scale: float = 1.0, beta: float = 0.0,
+                       precision: int = F32) -> None:
+        """M <- beta M + scale * network(X), X the descriptors of M's pattern."""
+        _check(_lib.bsm_mlp_predict_blocks(self.handle, int(precision), _ptr(X.contiguous()), float(scale),
+                                           float(beta), M.c))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.ctx.handle:
+            _lib.bsm_mlp_destroy(self.handle)
         self.handle = None
 
     def __del__(self):

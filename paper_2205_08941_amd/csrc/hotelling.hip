@@ -60,60 +60,83 @@ extern "C" int hotelling_inverse(bsm_ctx ctx, const bsm_matrix *S, const bsm_mat
             res->n_residuals++;
         };
 
-        if (!prm->init_given) {
+        BSM_REQUIRE(prm->init_given >= 0 && prm->init_given <= 2, BSM_EINVAL, "bad init_given");
+        res->start = prm->init_given ? 1 : 0;
+        auto plain_alpha = [&]() {
             const double rho = max_abs_row_sum(c, PS, Sd);
-            if (!(std::isfinite(rho) && rho > 0.0)) {
-                res->status = BSM_ENONFINITE;
-                return fail(BSM_ENONFINITE, "overlap matrix has a non-finite or zero row sum");
-            }
-            res->alpha = 1.0 / rho;
+            BSM_REQUIRE(std::isfinite(rho) && rho > 0.0, BSM_ENONFINITE,
+                        "overlap matrix has a non-finite or zero row sum");
+            return 1.0 / rho;
+        };
+        // plain start Z0 = alpha I into Z; T = Z0 S; r = its residual
+        auto start_plain = [&](double &r) {
+            res->alpha = plain_alpha();
             set_identity(c, PZ, res->alpha, Zd);
+            launch_product_f64(c, pZS, 1.0, PZ, Zd, PS, Sd, 0.0, PT, T.as<double>());
+            res->product_flops += pZS->flops;
+            r = residual(c, PT, T.as<double>(), nb);
+            res->start = 0;
+        };
+        double r = 0.0;
+        if (prm->init_given == 0) {
+            start_plain(r);
+        } else {
+            if (prm->init_given == 2) {   // Z holds a correction: Z0 = alpha I + Z
+                res->alpha = plain_alpha();
+                set_identity(c, PZ, res->alpha, Zw.as<double>());
+                axpby(c, nz, 1.0, Zw.as<double>(), 1.0, Zd);
+            }
+            launch_product_f64(c, pZS, 1.0, PZ, Zd, PS, Sd, 0.0, PT, T.as<double>());
+            res->product_flops += pZS->flops;
+            r = residual(c, PT, T.as<double>(), nb);
+            if (prm->init_given == 2) {
+                // residual of the plain start alpha I (held in Zw), computed aside in Tn
+                launch_product_f64(c, pZS, 1.0, PZ, Zw.as<double>(), PS, Sd, 0.0, PT, Tn.as<double>());
+                res->product_flops += pZS->flops;
+                const double rp = residual(c, PT, Tn.as<double>(), nb);
+                if (!(std::isfinite(r) && r < rp)) {
+                    BSM_HIP_TRY(hipMemcpyAsync(Zd, Zw.ptr, sizeof(double) * nz, hipMemcpyDeviceToDevice, c->stream));
+                    std::swap(T, Tn);
+                    r = rp;
+                    res->start = 0;
+                }
+            }
         }
-        launch_product_f64(c, pZS, 1.0, PZ, Zd, PS, Sd, 0.0, PT, T.as<double>());
-        res->product_flops += pZS->flops;
-        double r = residual(c, PT, T.as<double>(), nb);
         if (!std::isfinite(r)) {
             res->status = BSM_ENONFINITE;
             record(r);
             return fail(BSM_ENONFINITE, "Hotelling residual is not finite");
         }
         record(r);
-        const double r0 = r;
-        int status = BSM_OK;
+        // Z' = sym(mask_Z(2 Z - T Z)) until the tolerance, max_iter, stagnation or divergence
+        auto iterate = [&](double &rr, int &it) {
+            while (true) {
+                if (prm->tol > 0 && rr < prm->tol * std::sqrt(nb)) return (int)BSM_OK;
+                if (it == prm->max_iter) return prm->tol > 0 ? (int)BSM_ENOTCONV : (int)BSM_OK;
+                launch_product_f64(c, pTZ, 1.0, PT, T.as<double>(), PZ, Zd, 0.0, PZ, M.as<double>());
+                axpbypcz(c, nz, 2.0, Zd, -1.0, M.as<double>(), 0.0, Zw.as<double>());
+                symmetrize(c, PZ, Zw.as<double>());
+                launch_product_f64(c, pZS, 1.0, PZ, Zw.as<double>(), PS, Sd, 0.0, PT, Tn.as<double>());
+                res->product_flops += pTZ->flops + pZS->flops;
+                const double rn = residual(c, PT, Tn.as<double>(), nb);
+                if (!std::isfinite(rn)) return (int)BSM_ENONFINITE;
+                if (rn >= 0.99 * rr)   // no real progress: keep the current Z; the truncation floor or divergence
+                    return rr <= 0.1 * std::sqrt(nb) ? (int)BSM_OK : (int)BSM_EDIVERGED;
+                BSM_HIP_TRY(hipMemcpyAsync(Zd, Zw.ptr, sizeof(double) * nz, hipMemcpyDeviceToDevice, c->stream));
+                std::swap(T, Tn);
+                rr = rn;
+                ++it;
+                record(rr);
+            }
+        };
         int it = 0;
-        while (true) {
-            if (prm->tol > 0 && r < prm->tol * std::sqrt(nb)) {
-                status = BSM_OK;
-                break;
-            }
-            if (it == prm->max_iter) {
-                status = prm->tol > 0 ? BSM_ENOTCONV : BSM_OK;
-                break;
-            }
-            // Z' = sym(mask_Z(2 Z - T Z))
-            launch_product_f64(c, pTZ, 1.0, PT, T.as<double>(), PZ, Zd, 0.0, PZ, M.as<double>());
-            axpbypcz(c, nz, 2.0, Zd, -1.0, M.as<double>(), 0.0, Zw.as<double>());
-            symmetrize(c, PZ, Zw.as<double>());
-            launch_product_f64(c, pZS, 1.0, PZ, Zw.as<double>(), PS, Sd, 0.0, PT, Tn.as<double>());
-            res->product_flops += pTZ->flops + pZS->flops;
-            const double rn = residual(c, PT, Tn.as<double>(), nb);
-            if (!std::isfinite(rn)) {
-                status = BSM_ENONFINITE;
-                break;
-            }
-            if (rn > r0) {
-                status = BSM_EDIVERGED;
-                break;
-            }
-            if (rn >= r) {   // stagnation: keep the current Z
-                status = (r <= 0.1 * std::sqrt(nb)) ? BSM_OK : BSM_EDIVERGED;
-                break;
-            }
-            BSM_HIP_TRY(hipMemcpyAsync(Zd, Zw.ptr, sizeof(double) * nz, hipMemcpyDeviceToDevice, c->stream));
-            std::swap(T, Tn);
-            r = rn;
-            ++it;
+        int status = iterate(r, it);
+        if (prm->init_given == 2 && res->start == 1 && status != BSM_OK && status != BSM_ENOTCONV) {
+            // the given start failed: rerun from the plain start
+            start_plain(r);
             record(r);
+            it = 0;
+            status = std::isfinite(r) ? iterate(r, it) : (int)BSM_ENONFINITE;
         }
         BSM_HIP_TRY(hipStreamSynchronize(c->stream));
         res->iterations = it;

@@ -13,6 +13,7 @@
 // Every intermediate is held on a pattern wide enough for the blocks later
 // steps read, so E, N and their gradients are exact for the truncated L.
 #include "bsm_internal.h"
+#include "bsm_guess.h"
 
 #include <cmath>
 #include <functional>
@@ -126,6 +127,19 @@ struct lnv_state_s {
     int step(lnv_result *res);
     double init_flops = 0.0;
 
+    // E = 2 Tr KH and N = 2 Tr KS of the current L (X = LS, Y = LH, W = XX on P_X)
+    void energy(double &E, double &N)
+    {
+        mul(1.0, PL, L, PS, S, 0.0, X.p, X.d());
+        mul(1.0, PL, L, PH, H, 0.0, Y.p, Y.d());
+        mul(X, X, W);
+        double tr[4];
+        const double *a[4] = {X.d(), W.d(), X.d(), W.d()}, *b[4] = {Y.d(), Y.d(), X.d(), X.d()};
+        trace_products(c, 4, X.p, a, X.p, b, tr);
+        E = 2.0 * (3.0 * tr[0] - 2.0 * tr[1]);
+        N = 2.0 * (3.0 * tr[2] - 2.0 * tr[3]);
+    }
+
     double dot1(const Mat &A, const Mat &B)
     {
         const double *a = A.d(), *b = B.d();
@@ -187,6 +201,44 @@ extern "C" int lnv_state_reset(lnv_state *st, const lnv_params *prm, double *ini
         BSM_REQUIRE(prm->mode == LNV_CANONICAL || prm->mode == LNV_GRAND, BSM_EINVAL, "bad mode");
         st->reset(*prm);
         if (init_flops) *init_flops = st->init_flops;
+        return BSM_OK;
+    } catch (const Error &e) {
+        return fail(e.code, e.msg);
+    } catch (...) {
+        return fail(BSM_EINVAL, "unknown error");
+    }
+}
+
+extern "C" int lnv_state_reset_guess(lnv_state *st, const lnv_params *prm, const bsm_matrix *dL, double n_tol,
+                                     lnv_guess_result *out)
+{
+    try {
+        BSM_REQUIRE(st && prm && dL && out, BSM_EINVAL, "NULL argument");
+        BSM_REQUIRE(prm->mode == LNV_CANONICAL || prm->mode == LNV_GRAND, BSM_EINVAL, "bad mode");
+        BSM_REQUIRE(n_tol >= 0.0, BSM_EINVAL, "n_tol must be >= 0");
+        check_matrix(dL, "dL");
+        BSM_REQUIRE(dL->pattern == st->PL, BSM_EPATTERN, "dL must be on L's pattern");
+        BSM_REQUIRE(dL->blocks != st->L, BSM_EINVAL, "dL aliases L");
+        *out = lnv_guess_result{};
+        lnv_params p = *prm;
+        p.init_from_z = 1;
+        st->reset(p);                       // L = c mask_L(Z); products in FP64
+        st->flops = 0.0;
+        Context *c = st->c;
+        const int64_t nl = nelems(st->PL);
+        st->energy(out->E_plain, out->N_plain);
+        BSM_HIP_TRY(hipMemcpyAsync(st->t1.d(), st->L, sizeof(double) * nl, hipMemcpyDeviceToDevice, c->stream));
+        axpby(c, nl, 1.0, (const double *)dL->blocks, 1.0, st->L);
+        st->energy(out->E_guess, out->N_guess);
+        out->accepted = std::isfinite(out->E_guess) && std::isfinite(out->N_guess) &&
+                        std::fabs(out->N_guess - prm->n_electrons) <= n_tol * prm->n_electrons &&
+                        out->E_guess < out->E_plain;
+        if (!out->accepted)
+            BSM_HIP_TRY(hipMemcpyAsync(st->L, st->t1.d(), sizeof(double) * nl, hipMemcpyDeviceToDevice, c->stream));
+        BSM_HIP_TRY(hipStreamSynchronize(c->stream));
+        out->product_flops = st->init_flops + st->flops;
+        st->flops = 0.0;
+        st->prec = prm->product_precision;
         return BSM_OK;
     } catch (const Error &e) {
         return fail(e.code, e.msg);

@@ -1,17 +1,18 @@
-"""The C-ABI library loads without a GPU and exports every function include/bsm.h declares."""
+"""The C-ABI library loads without a GPU and exports every function include/*.h declares."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "bsm.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 LIB = os.path.join(ROOT, "paper_2205_08941_amd", "libbsm.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     text = "\n".join(l for l in text.splitlines() if not l.lstrip().startswith("typedef"))
     names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\([^;]*\)\s*;", text, flags=re.M)
@@ -21,7 +22,7 @@ def declared_functions():
 def test_header_declares_the_hot_path():
     names = declared_functions()
     for n in ["bsm_create_pattern", "bsm_multiply_truncate", "bsm_trace_product", "lnv_step",
-              "hotelling_inverse"]:
+              "hotelling_inverse", "bsm_mlp_train", "bsm_pair_descriptors", "lnv_state_reset_guess"]:
         assert n in names
 
 

@@ -13,7 +13,7 @@ def _rand_params(sh, seed, scale=0.3):
 
 
 def test_gradient_matches_central_differences():
-    sh = M.Shape(width=8, out_dim=5)
+    sh = M.Shape(width=8, out_dim=5, in_dim=16)
     rng = np.random.default_rng(1)
     X = rng.uniform(-1, 1, (23, 16))
     T = rng.uniform(-1, 1, (23, 5))
@@ -31,7 +31,7 @@ def test_gradient_matches_central_differences():
 def test_forward_permutation_network():
     # W1, W2 permutation matrices (not symmetric), biases 0, W3 picks the first outputs:
     # y_o = tanh(tanh(x_{q(p(o))})) with the weights read input-major.
-    sh = M.Shape(width=16, out_dim=3)
+    sh = M.Shape(width=16, out_dim=3, in_dim=16)
     p1 = np.roll(np.arange(16), 3)        # h1_o = tanh(x_{p1[o]})
     p2 = np.roll(np.arange(16), -5)       # h2_o = tanh(h1_{p2[o]})
     W1 = np.zeros((16, 16)); W1[p1, np.arange(16)] = 1.0
@@ -47,7 +47,7 @@ def test_forward_permutation_network():
 
 def test_forward_constant_layers():
     # W1 = W2 = 0: h1 = tanh(b1), h2 = tanh(b2) for every input; y = h2 W3 + b3
-    sh = M.Shape(width=4, out_dim=2)
+    sh = M.Shape(width=4, out_dim=2, in_dim=16)
     b1 = np.arctanh(np.array([0.5, -0.5, 0.25, 0.0]))
     b2 = np.arctanh(np.array([0.1, 0.2, 0.3, 0.4]))
     W3 = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0], [2.0, -1.0]])
@@ -57,7 +57,7 @@ def test_forward_constant_layers():
 
 
 def test_zero_last_layer_predicts_zero():
-    sh = M.Shape(width=8, out_dim=4)
+    sh = M.Shape(width=8, out_dim=4, in_dim=16)
     p = _rand_params(sh, 5)
     p[-(8 * 4 + 4):] = 0.0
     assert not np.any(M.forward(p, sh, np.random.default_rng(0).uniform(-1, 1, (9, 16))))
@@ -76,7 +76,7 @@ def test_adam_step_sizes():
 
 
 def test_training_fits_a_linear_target():
-    sh = M.Shape(width=16, out_dim=2)
+    sh = M.Shape(width=16, out_dim=2, in_dim=16)
     rng = np.random.default_rng(4)
     X = rng.uniform(-1, 1, (256, 16))
     T = np.stack([0.3 * X[:, 0] - 0.2 * X[:, 5], 0.1 * X[:, 3]], 1)
@@ -87,10 +87,11 @@ def test_training_fits_a_linear_target():
 
 def test_frames_on_the_ideal_lattice():
     pos, box, sub = synth.diamond_positions((2, 2, 2))
-    s, e = M.atom_frames(pos, box)
+    s, e, l, c = M.atom_frames(pos, box)
     assert np.array_equal(s, np.where(sub == 0, 1.0, -1.0))
-    # every bond direction is exactly the sublattice's tetrahedral direction
+    # every bond direction is exactly the sublattice's tetrahedral direction, every bond ideal
     assert np.allclose(e, s[:, None, None] * M.TETRA[None], atol=1e-12)
+    assert np.allclose(l, 5.43 * np.sqrt(3) / 4, atol=1e-12) and np.allclose(c, 0.0, atol=1e-12)
 
 
 def test_descriptors_of_the_ideal_lattice():
@@ -112,21 +113,39 @@ def test_descriptors_of_the_ideal_lattice():
     assert np.allclose(X[dg][:, [0, 1, 2, 3, 4, 8, 9, 10, 11, 12, 13, 14, 15]], 0.0)
     assert np.allclose(X[dg, 5], 1.0)
     # reflection: (j, i) has -r, the same distance, swapped sublattices and cosine groups negated
-    Xt = X.reshape(n, n, 16).transpose(1, 0, 2).reshape(-1, 16)
+    Xt = X.reshape(n, n, 32).transpose(1, 0, 2).reshape(-1, 32)
     off = ~dg
     assert np.allclose(Xt[off, 0:3], -X[off, 0:3], atol=1e-14)
     assert np.allclose(Xt[off, 3:6], X[off, 3:6], atol=1e-14)
     assert np.array_equal(Xt[off, 6], X[off, 7])
     assert np.allclose(Xt[off, 8:12], -X[off, 12:16], atol=1e-14)
+    # no strain on the ideal lattice, and the two padding features are zero
+    assert np.allclose(X[:, 16:32], 0.0, atol=1e-11)
 
 
 def test_frames_of_a_displaced_frame_keep_the_sublattices():
     sy = synth.displaced_frame(2, 4, seed=10000, sigma=0.05)
     _, _, sub = synth.diamond_positions((2, 2, 2))
-    s, e = M.atom_frames(sy.positions, sy.box)
+    s, e, l, c = M.atom_frames(sy.positions, sy.box)
     assert np.array_equal(s, np.where(sub == 0, 1.0, -1.0))
     # each hybrid slot holds a different neighbour, within a few degrees of the ideal direction
     cos = np.einsum("nac,ac->na", e, M.TETRA) * s[:, None]
     assert cos.min() > 0.98
     for i in range(len(s)):
         assert len({tuple(np.round(v, 12)) for v in e[i]}) == 4
+    # lengths stay within a few sigma of the ideal bond; l[a] e[a] sum to 4 c (all four used once)
+    assert np.abs(l - 5.43 * np.sqrt(3) / 4).max() < 0.5
+    assert np.allclose((l[:, :, None] * e).sum(1), 4.0 * c, atol=1e-12)
+
+
+def test_descriptors_are_translation_invariant_and_swap_under_reflection():
+    sy = synth.displaced_frame(2, 4, seed=10001, sigma=0.05)
+    n = sy.natoms
+    rows, cols = np.repeat(np.arange(n), n), np.tile(np.arange(n), n)
+    X = M.pair_descriptors(sy.positions, sy.box, rows, cols, 8.0, M.atom_frames(sy.positions, sy.box))
+    moved = np.mod(sy.positions + np.array([1.3, -2.9, 7.7]), sy.box)
+    X2 = M.pair_descriptors(moved, sy.box, rows, cols, 8.0, M.atom_frames(moved, sy.box))
+    assert np.allclose(X, X2, atol=1e-12)
+    Xt = X.reshape(n, n, 32).transpose(1, 0, 2).reshape(-1, 32)
+    assert np.allclose(Xt[:, 16:20], X[:, 20:24]) and np.allclose(Xt[:, 24:27], X[:, 27:30])
+    assert np.abs(X[:, 16:30]).max() > 0.1      # displacements do show up
