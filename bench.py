@@ -39,9 +39,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="si4096_b9", choices=["si4096_b9", "si64_b4", "batch64"],
+    ap.add_argument("--workload", default="si4096_b9",
+                    choices=["si4096_b9", "si64_b4", "batch64", "si4096_b9_mixed", "guess"],
                     help="batch64: 64 uneven systems (512-4096 atoms, b = 4 and 9), the 16 A x 16 A -> 16 A "
-                         "product of each, per-product launches against one tuned persistent launch")
+                         "product of each, per-product launches against one tuned persistent launch; "
+                         "si4096_b9_mixed: the solve with BF16 then FP32 products and 3 FP64 steps against "
+                         "the FP64 solve; guess: networks trained on 512-atom displaced frames, a 4096-atom "
+                         "displaced frame solved from the learned and from the plain starts")
+    ap.add_argument("--guess-train", type=int, default=12, help="training frames of the guess workload")
+    ap.add_argument("--guess-cells", type=int, default=8, help="cells per side of the guess test frame")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--max-lnv", type=int, default=300)
     ap.add_argument("--tol-e", type=float, default=1e-8)
@@ -179,6 +185,93 @@ def batch_mode(args):
     print(json.dumps(out), flush=True)
 
 
+
+def _solver(ctx, s):
+    import torch
+    import paper_2205_08941_amd as bsm
+    dev = ctx.device
+    pos = torch.tensor(s.positions, dtype=torch.float64, device=dev)
+    P = {k: bsm.Pattern(ctx, pos, s.box, s.cutoffs[k], s.b) for k in ("S", "Z", "L")}
+    S, H, Z, L = bsm.Matrix(P["S"]), bsm.Matrix(P["S"]), bsm.Matrix(P["Z"]), bsm.Matrix(P["L"])
+    bsm.fill_blocks(S, s.S.rows, s.S.cols, s.S.blocks)
+    bsm.fill_blocks(H, s.H.rows, s.H.cols, s.H.blocks)
+    return P, S, H, Z, L
+
+
+def mixed_mode(args):
+    """Time to the converged energy: FP64 products against BF16 -> FP32 -> 3 x FP64 stages."""
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    s = synth.si4096_b9()
+    ctx = bsm.Context(0)
+    P, S, H, Z, L = _solver(ctx, s)
+    bsm.hotelling_inverse(S, Z, max_iter=100, tol=1e-12)
+    lnv = bsm.LNV(S, H, Z, L, s.n_electrons, tol_E=args.tol_e, init_from_z=True)
+    stages = [(bsm.BF16, 30, 0.0, True), (bsm.F32, 60, 1e-6, True), (bsm.F64, 3, 0.0, False)]
+    out = {}
+    for tag, sched in (("f64", [(bsm.F64, args.max_lnv, args.tol_e, False)]), ("mixed", stages)):
+        for rep in range(args.warmup + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            hr = bsm.hotelling_inverse(S, Z, max_iter=100, tol=1e-12)
+            lnv.reset(init_from_z=True)
+            r = lnv.solve(sched)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+        e_idem = lnv.idempotency_error()
+        out[tag] = dict(seconds=round(dt, 3), E=r["E"], iterations=r["iterations"], converged=r["converged"],
+                        status=r["status"], idempotency_error=e_idem, hotelling=hr.iterations)
+        log(f"[mixed] {tag}: {dt:.2f} s, iterations {r['iterations']}, E {r['E']:.10f}, e_idem {e_idem:.3e}")
+    dE = abs(out["mixed"]["E"] - out["f64"]["E"]) / s.natoms
+    res = {"metric": "s per converged LNV solve, 4096-atom 9-orb, mixed-precision products",
+           "value": out["mixed"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+           "ms_per_step": out["mixed"]["seconds"] * 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16/f32 products, f64 traces", "data": "synthetic",
+           "config": {"workload": "si4096_b9: Hotelling + LNV, BF16 (30) -> FP32 (60, 1e-6 Ha) -> 3 FP64 steps"},
+           "f64": out["f64"], "mixed": out["mixed"], "dE_per_atom_Ha": dE,
+           "speedup_vs_f64": round(out["f64"]["seconds"] / out["mixed"]["seconds"], 3)}
+    print(json.dumps(res), flush=True)
+
+
+def guess_mode(args):
+    """Learned starts: train on 512-atom displaced frames, solve a larger held-out frame both ways."""
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    from paper_2205_08941_amd import guess
+    ctx = bsm.Context(0)
+    t = time.perf_counter()
+    frames = [guess.Frame(ctx, synth.displaced_frame((4, 4, 4), 9, seed=10000 + k)) for k in range(args.guess_train)]
+    netZ, netL, info = guess.train_guess(ctx, frames, epochs=30, batch=4096, lr=1e-3, log=log)
+    train_s = time.perf_counter() - t
+    gen_s = sum(r["seconds"] for r in info["solves"])
+    for f in frames:
+        f.close()
+    del frames
+    torch.cuda.empty_cache()
+    n = args.guess_cells
+    f = guess.Frame(ctx, synth.displaced_frame((n, n, n), 9, seed=20000))
+    log(f"[guess] trained in {train_s:.1f} s ({gen_s:.1f} s of solves); test frame {f.sys.natoms} atoms")
+    f.solve_plain(tol_E=args.tol_e)            # warm-up: patterns, plans
+    p = f.solve_plain(tol_E=args.tol_e)
+    g = f.solve_guess(netZ, netL, tol_E=args.tol_e, precision=bsm.BF16)
+    log(f"[guess] plain {p['hotelling']} + {p['lnv']} in {p['seconds']:.2f} s; learned {g['hotelling']} + "
+        f"{g['lnv']} in {g['seconds']:.2f} s; dE {g['E'] - p['E']:.2e} Ha")
+    res = {"metric": f"s per converged LNV solve, {f.sys.natoms}-atom 9-orb displaced frame, learned start",
+           "value": round(g["seconds"], 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": round(g["seconds"] * 1e3, 1), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 solve, bf16 network", "data": "synthetic",
+           "config": {"workload": f"train on {args.guess_train} 512-atom frames (sigma 0.05 A), test on "
+                                  f"{f.sys.natoms} atoms", "train_samples_L": info["samples_L"],
+                      "train_samples_Z": info["samples_Z"]},
+           "plain": p, "learned": g, "dE_per_atom_Ha": abs(g["E"] - p["E"]) / f.sys.natoms,
+           "speedup_vs_plain": round(p["seconds"] / g["seconds"], 3), "train_seconds": round(train_s, 2),
+           "train_solve_seconds": round(gen_s, 2),
+           "loss_L": [info["losses_L"][0], info["losses_L"][-1]], "loss_Z": [info["losses_Z"][0], info["losses_Z"][-1]]}
+    print(json.dumps(res), flush=True)
+
+
 def cpu_baseline(args):
     """The FP64 oracle timed on a bounded sample: rows of the dominant product class."""
     import numpy as np
@@ -239,6 +332,12 @@ def main():
         return
     if args.workload == "batch64":
         batch_mode(args)
+        return
+    if args.workload == "si4096_b9_mixed":
+        mixed_mode(args)
+        return
+    if args.workload == "guess":
+        guess_mode(args)
         return
     s = synth.si4096_b9() if args.workload == "si4096_b9" else synth.si64_b4()
     cut = s.cutoffs

@@ -48,6 +48,9 @@ __global__ void k_zero_counters(int n, unsigned *c)
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
 }
 
+// One kernel per batch precision (F64 = true: the DPP kinds; false: the FP32
+// kinds), so that each is compiled with the registers its own tiles need.
+template <bool F64>
 __global__ __launch_bounds__(256) void k_product_batch(const BatchDesc *__restrict__ desc, const int2 *__restrict__ items,
                                                        const int64_t *__restrict__ qbeg, int nq,
                                                        unsigned *__restrict__ counters, const double *__restrict__ zblk)
@@ -64,23 +67,21 @@ __global__ __launch_bounds__(256) void k_product_batch(const BatchDesc *__restri
         const int2 it = items[base + t];
         const int p = __builtin_amdgcn_readfirstlane(it.x);
         const BatchDesc d = desc[p];
-        switch (__builtin_amdgcn_readfirstlane(d.kind)) {
-            case kKindF64Dpp9:
+        const int kind = __builtin_amdgcn_readfirstlane(d.kind);
+        if constexpr (F64) {
+            if (kind == kKindF64Dpp9)
                 tile_dpp<9, 4>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A, (const double *)d.B, zblk, d.C,
                                d.alpha, d.beta);
-                break;
-            case kKindF64Dpp4:
+            else
                 tile_dpp<4, 4>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A, (const double *)d.B, zblk, d.C,
                                d.alpha, d.beta);
-                break;
-            case kKindF32b9:
+        } else {
+            if (kind == kKindF32b9)
                 tile_sgpr<9, 4, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A, (const float *)d.B, d.C,
                                        d.alpha, d.beta);
-                break;
-            default:
+            else
                 tile_sgpr<4, 4, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A, (const float *)d.B, d.C,
                                        d.alpha, d.beta);
-                break;
         }
     }
 }
@@ -206,8 +207,12 @@ void bsm_batch_s::run(const bsm_batch_config &cfg)
     }
     k_zero_counters<<<1, 64, 0, st>>>(cfg.queues, counters.as<unsigned>());
     const int blocks = kCUs * cfg.waves_per_cu / 4;
-    k_product_batch<<<blocks, 256, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(), cfg.queues,
-                                            counters.as<unsigned>(), c->zero_block.as<double>());
+    if (prec == BSM_F64)
+        k_product_batch<true><<<blocks, 256, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(),
+                                                      cfg.queues, counters.as<unsigned>(), c->zero_block.as<double>());
+    else
+        k_product_batch<false><<<blocks, 256, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(),
+                                                       cfg.queues, counters.as<unsigned>(), c->zero_block.as<double>());
     BSM_HIP_TRY(hipGetLastError());
 }
 
