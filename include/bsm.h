@@ -116,15 +116,19 @@ typedef struct {
 } bsm_product_stat;
 
 /* Rows of C per wavefront tile in product plans built from now on: 2, 4 or 8
- * (0 restores the default for the orbital count).  Larger values reuse each B
- * block across more rows at the cost of idle lanes.  Clears cached plans. */
+ * (0 restores the default for the orbital count); variant 2 plans always use
+ * 16-row workgroup tiles.  Larger values reuse each B block across more rows at
+ * the cost of idle lanes.  Clears cached plans (destroy batches first). */
 int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
 /* FP64 product kernel of plans built from now on: 0 = the uniform A block read
  * through the scalar cache into SGPRs; 1 = A held in VGPRs and broadcast by DPP
- * (b = 4 and 9, rows per wave 2 or 4; other shapes use 0); -1 = default (1 for
- * b = 4 and 9, else 0).  Variant 1 multiplies
- * absent (k, j) blocks by zero instead of skipping them, so a non-finite block
- * of A can make other blocks of its output row non-finite.  Clears cached plans. */
+ * (b = 4 and 9, rows per wave 2 or 4; other shapes use 0); 2 = workgroup tiles
+ * of 16 rows (4 wavefronts of 4 rows sharing the tile's B blocks, staged in
+ * LDS, A as in 1; b = 4 and 9, else 0); -1 = default (1 for b = 4 and 9, else
+ * 0).  Variants 1 and 2 multiply absent (k, j) blocks by zero instead of
+ * skipping them, so a non-finite block of A can make other blocks of its
+ * output row non-finite.  Clears cached plans (a bsm_batch made before keeps
+ * pointers to them: destroy batches first). */
 int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant);
 /* Launch order of product tiles in plans built from now on: tiles of `span`
  * consecutive row groups are interleaved by column position (1 = group by

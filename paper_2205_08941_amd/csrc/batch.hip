@@ -246,8 +246,8 @@ int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *
         check_same_shape(&A[p], &C[p]);
         const int b = C[p].pattern->b;
         BSM_REQUIRE(b == 4 || b == 9, BSM_EINVAL, "batched products support b = 4 and 9");
-        Plan *plan = get_plan(c, A[p].pattern, B[p].pattern, C[p].pattern);
-        BSM_REQUIRE(plan->G == 4, BSM_EINVAL, "batched products need plans with 4 rows per wave");
+        // wave tiles of 4 rows: DPP for FP64, SGPR for the rounded operands
+        Plan *plan = get_plan_kind(c, A[p].pattern, B[p].pattern, C[p].pattern, precision == BSM_F64 ? 1 : 0, 4);
         bt->plans.push_back(plan);
         bt->pa.push_back(A[p].pattern);
         bt->pb.push_back(B[p].pattern);

@@ -61,7 +61,7 @@ struct Plan {
     double cutoffs[3] = {0, 0, 0};
     int natoms = 0, b = 0;
     int G = 0;                  // rows per wavefront tile
-    int variant = 0;            // 0: A through SGPRs, 1: A in VGPRs with DPP broadcast
+    int variant = 0;            // 0: A through SGPRs, 1: A in VGPRs with DPP broadcast, 2: workgroup tiles
     int jt = 0;                 // output block columns per wavefront tile (64 / b)
     int64_t ntiles = 0;
     int64_t nentries = 0;
@@ -87,7 +87,7 @@ class Context {
     int group_span = 4;         // row groups interleaved in product launch order
     // derived patterns (same atoms, another cutoff), owned here, keyed by (source id, cutoff)
     std::map<std::pair<uint64_t, double>, bsm_pattern_s *> derived;
-    std::map<std::tuple<uint64_t, uint64_t, uint64_t>, std::unique_ptr<Plan>> plans;
+    std::map<std::tuple<uint64_t, uint64_t, uint64_t, int, int>, std::unique_ptr<Plan>> plans;   // (A, B, C, variant, rows)
     // reduction scratch
     DevBuf red_partials;        // double[kRedBlocks * kRedSlots]
     DevBuf err_flag;            // int
@@ -154,6 +154,9 @@ bsm_pattern_s *derived_pattern(const bsm_pattern_s *p, double cutoff);
 const bsm_pattern_s *derived_pattern_cached(const bsm_pattern_s *p, double cutoff);
 void destroy_pattern(bsm_pattern_s *p);
 Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C);
+// A plan of a given kernel variant (0: SGPR, 1: DPP wave tiles, 2: workgroup tiles) and rows per tile.
+Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C,
+                    int variant, int G);
 
 // ---------------------------------------------------------------- launches
 void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,

@@ -35,6 +35,7 @@ namespace {
 
 constexpr int kXcd = 8;       // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int kWaves = 4;     // wavefronts (tiles) per workgroup
+constexpr int kMaxRows = 16;  // rows of a tile, at most
 
 __device__ inline int64_t logical_workgroup(int64_t nwg_padded)
 {
@@ -67,6 +68,19 @@ __global__ __launch_bounds__(256) void k_product_f64_dpp(
     const int64_t slot = logical_workgroup(nwg_padded) * kWaves + (threadIdx.x >> 6);
     if (slot >= ntiles) return;
     tile_dpp<B, G>(order[slot], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta);
+}
+
+// One workgroup tile (16 rows x JT columns) per workgroup.
+template <int B>
+__global__ __launch_bounds__(256) void k_product_wg(
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
+    const double *__restrict__ vB, double *__restrict__ vC, double alpha, double beta)
+{
+    __shared__ double lds[2 * WgTile<B>::kStage];
+    const int64_t t = logical_workgroup(nwg_padded);
+    if (t >= ntiles) return;   // uniform over the workgroup
+    tile_wg<B>(order[t], hdr, ebeg, ent, vA, vB, vC, alpha, beta, lds);
 }
 
 // ---------------------------------------------------------------- operand rounding
@@ -112,7 +126,7 @@ __global__ void k_group_union(int n, int G, const int *__restrict__ rpC, const i
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int ng = (n + G - 1) / G;
     if (g >= ng) return;
-    int p[8], pe[8];
+    int p[kMaxRows], pe[kMaxRows];
     const int i0 = g * G, gr = min(G, n - i0);
     for (int a = 0; a < gr; ++a) {
         p[a] = rpC[i0 + a];
@@ -139,7 +153,7 @@ __global__ void k_group_tiles(int n, int G, int jt, const int *__restrict__ rpC,
     const int ng = (n + G - 1) / G;
     if (g >= ng) return;
     const int hs = G + G * jt;
-    int p[8], pe[8];
+    int p[kMaxRows], pe[kMaxRows];
     const int i0 = g * G, gr = min(G, n - i0);
     for (int a = 0; a < gr; ++a) {
         p[a] = rpC[i0 + a];
@@ -187,13 +201,11 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restr
     if (t >= ntiles) return;
     const int hs = G + G * jt, es = G + jt;
     const int *h = hdr + t * hs;
-    int pa[8], pae[8], pb[64], pbe[64], jcol[64];
-    bool crow[8][64];
+    int pa[kMaxRows], pae[kMaxRows], pb[64], pbe[64], jcol[64];
     for (int a = 0; a < G; ++a) {
         const int i = h[a];
         pa[a] = (i >= 0) ? rpA[i] : 0;
         pae[a] = (i >= 0) ? rpA[i + 1] : 0;
-        for (int x = 0; x < jt; ++x) crow[a][x] = h[G + a * jt + x] >= 0;
     }
     for (int x = 0; x < jt; ++x) {
         const int j = tcols[t * jt + x];
@@ -209,7 +221,7 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restr
         for (int a = 0; a < G; ++a)
             if (pa[a] < pae[a]) k = min(k, cA[pa[a]]);
         if (k == 0x7fffffff) break;
-        int aslot[8];
+        int aslot[kMaxRows];
         for (int a = 0; a < G; ++a) {
             aslot[a] = -1;
             if (pa[a] < pae[a] && cA[pa[a]] == k) aslot[a] = pa[a]++;
@@ -222,7 +234,7 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restr
             while (pb[x] < pbe[x] && cB[pb[x]] < k) ++pb[x];
             if (pb[x] < pbe[x] && cB[pb[x]] == k) bslot[x] = tmB[pb[x]];   // slot of (k, j)
             if (bslot[x] < 0) continue;
-            for (int a = 0; a < G; ++a) ntri += (aslot[a] >= 0 && crow[a][x]) ? 1 : 0;
+            for (int a = 0; a < G; ++a) ntri += (aslot[a] >= 0 && h[G + a * jt + x] >= 0) ? 1 : 0;
         }
         if (ntri == 0) continue;
         if (MODE == 1) {
@@ -301,10 +313,24 @@ void launch_dpp(hipStream_t st, const Plan *plan, const double *A, const double 
 }
 
 template <int B>
+void launch_wg(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
+               double beta)
+{
+    const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
+    k_product_wg<B><<<(unsigned)nwg_padded, 256, 0, st>>>(plan->ntiles, nwg_padded, plan->order.as<int>(),
+                                                         plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+                                                         plan->ent.as<int>(), A, Bm, C, alpha, beta);
+}
+
+template <int B>
 void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
               double beta, const double *zblk)
 {
     if constexpr (B == 9 || B == 4) {
+        if (plan->variant == 2) {
+            launch_wg<B>(st, plan, A, Bm, C, alpha, beta);
+            return;
+        }
         if (plan->variant == 1) {
             switch (plan->G) {
                 case 2: launch_dpp<B, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
@@ -346,7 +372,7 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
 {
     hipStream_t st = ctx->stream;
     const int n = PC->natoms, jt = 64 / PC->b;
-    BSM_REQUIRE(G == 2 || G == 4 || G == 8, BSM_EINVAL, "rows per wave must be 2, 4 or 8");
+    BSM_REQUIRE(G == 2 || G == 4 || G == 8 || G == kMaxRows, BSM_EINVAL, "rows per tile must be 2, 4, 8 or 16");
     plan->G = G;
     plan->jt = jt;
     const int ng = (n + G - 1) / G;
@@ -461,6 +487,7 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
         return;
     }
     BSM_REQUIRE(prec == BSM_F32 || prec == BSM_BF16, BSM_EINVAL, "precision must be F64, F32 or BF16");
+    if (plan->G > 8) plan = get_plan_kind(ctx, PA, PB, PC, 0, default_rows_per_wave(PC->b));   // wave tiles
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
     const int64_t na = nelems(PA), nb = nelems(PB);
@@ -488,9 +515,10 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     }
 }
 
-Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C)
+Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C,
+                    int variant, int G)
 {
-    auto key = std::make_tuple(A->id, B->id, C->id);
+    auto key = std::make_tuple(A->id, B->id, C->id, variant, G);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) return it->second.get();
     std::unique_ptr<Plan> plan(new Plan());
@@ -502,12 +530,19 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
     plan->cutoffs[2] = C->cutoff;
     plan->natoms = C->natoms;
     plan->b = C->b;
-    const int G = ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b);
     build_plan(ctx, A, B, C, plan.get(), G);
-    plan->variant = ctx->product_variant >= 0 ? ctx->product_variant : default_variant(C->b);
+    plan->variant = variant;
     Plan *raw = plan.get();
     ctx->plans[key] = std::move(plan);
     return raw;
+}
+
+Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C)
+{
+    int variant = ctx->product_variant >= 0 ? ctx->product_variant : default_variant(C->b);
+    if (variant == 2 && C->b != 9 && C->b != 4) variant = 0;
+    const int G = variant == 2 ? kMaxRows : (ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b));
+    return get_plan_kind(ctx, A, B, C, variant, G);
 }
 
 }  // namespace bsm

@@ -311,5 +311,145 @@ __device__ inline void tile_dpp(int64_t tile, const int *__restrict__ hdr, const
     }
 }
 
+// ---------------------------------------------------------------- workgroup tiles
+// One tile of 16 rows x JT columns per workgroup of 4 wavefronts; wave w owns
+// rows 4w .. 4w+3 with the lane layout of tile_dpp.  All four waves read the
+// same B_kj blocks, so the workgroup stages them in LDS, two entries at a time
+// (double-buffered: the next pair is fetched from global memory into
+// registers while the current pair is multiplied, then written to the other
+// buffer; one barrier per pair).  Absent (k, j) blocks are staged as zeros.  A
+// blocks belong to single waves and are loaded as in tile_dpp.  An entry in
+// which none of a wave's rows has an A block costs that wave no FMAs.
+template <int B> struct WgTile {
+    static constexpr int kJT = 64 / B, kBB = B * B;
+    static constexpr int kStage = 2 * kJT * kBB;   // doubles per LDS buffer (two entries)
+};
+
+template <int B>
+__device__ inline void tile_wg(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
+                               const int *__restrict__ ent, const double *__restrict__ vA,
+                               const double *__restrict__ vB, double *__restrict__ vC, double alpha, double beta,
+                               double *__restrict__ lds)
+{
+    constexpr int JT = WgTile<B>::kJT, BB = WgTile<B>::kBB, STAGE = WgTile<B>::kStage;
+    constexpr int NA = (BB + 15) / 16;
+    constexpr int G = 16, GW = 4;                 // rows per tile, rows per wave
+    constexpr int HS = G + G * JT, ES = G + JT;
+    constexpr int U = (STAGE + 255) / 256;        // staged doubles per thread
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, l16 = lane & 15;
+    const int jl0 = lane / B, c = lane - jl0 * B;
+    const bool lane_ok = jl0 < JT;
+    const int jl = lane_ok ? jl0 : JT - 1;
+    const int *h = hdr + tile * HS;
+    int cs[GW];
+    bool cact[GW];
+#pragma unroll
+    for (int a = 0; a < GW; ++a) {
+        cs[a] = lane_ok ? h[G + (GW * w + a) * JT + jl] : -1;
+        cact[a] = cs[a] >= 0;
+    }
+    double acc[GW][B];
+#pragma unroll
+    for (int a = 0; a < GW; ++a)
+#pragma unroll
+        for (int r = 0; r < B; ++r) acc[a][r] = 0.0;
+
+    const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
+    const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
+    const int n = (int)(e1 - e0);                  // even
+    const int *entg = ent + e0 * ES;
+    const_as4<int> *entu = (const_as4<int> *)entg;
+
+    // Staging pipeline over pairs of entries (stages): the B slots of stage
+    // s + 2 and the B values of stage s + 1 are loaded while stage s is
+    // multiplied, so neither the slot nor the value load stalls the barrier.
+    // Thread tid stages doubles tid + 256 u of a stage.
+    int sl[U], sl2[U];
+    double pf[U];
+    auto fetch_slots = [&](int (&dst)[U], int q) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + 256 * u;
+            dst[u] = -1;
+            if (idx < STAGE) {
+                const int e = idx / (JT * BB), col = (idx - e * (JT * BB)) / BB;
+                if (q + e < n) dst[u] = entg[(int64_t)(q + e) * ES + G + col];
+            }
+        }
+    };
+    auto fetch_values = [&](const int (&src)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + 256 * u;
+            const int el = (idx % (JT * BB)) % BB;
+            pf[u] = src[u] >= 0 ? vB[(int64_t)src[u] * BB + el] : 0.0;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + 256 * u;
+            if (idx < STAGE) lds[buf * STAGE + idx] = pf[u];
+        }
+    };
+    auto read_b = [&](double (&bv)[B], int buf, int e) {
+        const double *p = lds + buf * STAGE + e * (JT * BB) + jl * BB + c;
+#pragma unroll
+        for (int m = 0; m < B; ++m) bv[m] = p[m * B];
+    };
+    // A blocks of one entry for this wave's rows (rows without a block load nothing)
+    auto load_rows = [&](double (&x)[GW][NA], int (&as)[GW], int q) {
+#pragma unroll
+        for (int a = 0; a < GW; ++a) {
+            as[a] = q < n ? entu[(int64_t)q * ES + GW * w + a] : -1;
+            if (as[a] >= 0) load_a<B, NA>(x[a], vA, as[a], l16);
+        }
+    };
+
+    double xa[GW][NA], xb[GW][NA], bv[B];
+    int asa[GW], asb[GW];
+    fetch_slots(sl, 0);
+    fetch_values(sl);
+    store(0);
+    fetch_slots(sl, 2);
+    load_rows(xa, asa, 0);
+    __syncthreads();
+    for (int q = 0; q < n; q += 2) {
+        const int buf = (q >> 1) & 1;
+        const bool more = q + 2 < n;
+        if (more) {
+            fetch_values(sl);            // stage q + 2
+            fetch_slots(sl2, q + 4);     // stage q + 4
+        }
+        load_rows(xb, asb, q + 1);
+        read_b(bv, buf, 0);
+        dpp_entry<B, GW, NA>(asa, xa, bv, acc);
+        load_rows(xa, asa, q + 2);
+        read_b(bv, buf, 1);
+        dpp_entry<B, GW, NA>(asb, xb, bv, acc);
+        if (more) {
+            store(buf ^ 1);
+#pragma unroll
+            for (int u = 0; u < U; ++u) sl[u] = sl2[u];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < GW; ++a) {
+        if (!cact[a]) continue;
+        double *cp = vC + (int64_t)cs[a] * BB + c;
+        if (beta == 0.0) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
+        }
+    }
+}
 
 }  // namespace bsm

@@ -57,6 +57,7 @@ SYSTEMS = {
     "si64_disp": lambda: synth.make_system("d", 2, 4, synth.SMALL_CUTOFFS, 3, displacement_sigma=0.2),
     "ortho_2x3x4": lambda: synth.make_system("o", (2, 3, 4), 4, synth.SMALL_CUTOFFS, 4, displacement_sigma=0.05),
     "si256_disp": lambda: synth.make_system("d2", (4, 4, 2), 4, synth.SMALL_CUTOFFS, 5, displacement_sigma=0.1),
+    "si216_disp": lambda: synth.make_system("d3", (3, 3, 3), 4, synth.SMALL_CUTOFFS, 6, displacement_sigma=0.1),
 }
 
 
@@ -128,14 +129,17 @@ def test_product_parity(bsm, ctx, b):
         assert bsm.product_flops(gp[ra], gp[rb], gp[rc]) == 2.0 * b ** 3 * tri
 
 
-@pytest.mark.parametrize("variant,rows", [(0, 2), (0, 4), (0, 8), (1, 2), (1, 4)])
+@pytest.mark.parametrize("variant,rows,system", [(0, 2, "si256_disp"), (0, 4, "si256_disp"), (0, 8, "si256_disp"),
+                                                  (1, 2, "si256_disp"), (1, 4, "si256_disp"), (2, 0, "si256_disp"),
+                                                  (2, 0, "si216_disp")])
 @pytest.mark.parametrize("b", [4, 9])
-def test_product_kernel_variants(bsm, b, variant, rows):
-    """Every product kernel variant and rows-per-wave choice gives the oracle's result."""
+def test_product_kernel_variants(bsm, b, variant, rows, system):
+    """Every product kernel variant and rows-per-wave choice gives the oracle's result
+    (216 atoms: the last 16-row workgroup tile is half empty)."""
     ctx = bsm.Context(0)
     ctx.set_product_variant(variant)
     ctx.set_rows_per_wave(rows)
-    s = SYSTEMS["si256_disp"]()
+    s = SYSTEMS[system]()
     say(f"product variant={variant} rows={rows} b={b}")
     gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
     op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
