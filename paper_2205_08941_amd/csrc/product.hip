@@ -83,6 +83,20 @@ __global__ __launch_bounds__(256) void k_product_wg(
     tile_wg<B>(order[t], hdr, ebeg, ent, vA, vB, vC, alpha, beta, lds);
 }
 
+// One wave tile per one-wave workgroup, operands through a per-wave LDS ring.
+template <int B, int G, int D>
+__global__ __launch_bounds__(64) void k_product_ring(
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
+    const double *__restrict__ vB, const double *__restrict__ zblk, double *__restrict__ vC, double alpha,
+    double beta)
+{
+    __shared__ __attribute__((aligned(16))) char ring[D * RingEntry<B, G>::kBytes];
+    const int64_t t = logical_workgroup(nwg_padded);
+    if (t >= ntiles) return;
+    tile_ring<B, G, D>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta, (lds_char_t *)ring);
+}
+
 // ---------------------------------------------------------------- operand rounding
 // FP64 -> FP32 (round to nearest even); for BF16, the FP32 value rounded again
 // to 8 significant bits (nearest even, Inf kept, NaN kept quiet), stored as FP32.
@@ -322,11 +336,31 @@ void launch_wg(hipStream_t st, const Plan *plan, const double *A, const double *
                                                          plan->ent.as<int>(), A, Bm, C, alpha, beta);
 }
 
+template <int B, int G, int D>
+void launch_ring(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
+                 double beta, const double *zblk)
+{
+    const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
+    k_product_ring<B, G, D><<<(unsigned)nwg_padded, 64, 0, st>>>(plan->ntiles, nwg_padded, plan->order.as<int>(),
+                                                                plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+                                                                plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta);
+}
+
 template <int B>
 void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
               double beta, const double *zblk)
 {
     if constexpr (B == 9 || B == 4) {
+        if (plan->variant == 3 || plan->variant == 4) {   // LDS ring, depth 3 or 2
+            const bool deep = plan->variant == 3;
+            switch (plan->G) {
+                case 2: deep ? launch_ring<B, 2, 3>(st, plan, A, Bm, C, alpha, beta, zblk)
+                             : launch_ring<B, 2, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                case 4: deep ? launch_ring<B, 4, 3>(st, plan, A, Bm, C, alpha, beta, zblk)
+                             : launch_ring<B, 4, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                default: break;
+            }
+        }
         if (plan->variant == 2) {
             launch_wg<B>(st, plan, A, Bm, C, alpha, beta);
             return;
@@ -365,7 +399,7 @@ void launch_b32(hipStream_t st, const Plan *plan, const float *A, const float *B
 }  // namespace
 
 int default_rows_per_wave(int b) { return b >= 5 ? 4 : (b == 4 ? 4 : 2); }
-int default_variant(int b) { return (b == 9 || b == 4) ? 1 : 0; }
+int default_variant(int b) { return b == 9 ? 4 : (b == 4 ? 1 : 0); }
 
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
                 Plan *plan, int G)
@@ -540,7 +574,7 @@ Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B
 Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C)
 {
     int variant = ctx->product_variant >= 0 ? ctx->product_variant : default_variant(C->b);
-    if (variant == 2 && C->b != 9 && C->b != 4) variant = 0;
+    if (variant >= 2 && C->b != 9 && C->b != 4) variant = 0;
     const int G = variant == 2 ? kMaxRows : (ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b));
     return get_plan_kind(ctx, A, B, C, variant, G);
 }

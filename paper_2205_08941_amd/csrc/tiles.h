@@ -452,4 +452,161 @@ __device__ inline void tile_wg(int64_t tile, const int *__restrict__ hdr, const 
     }
 }
 
+// ---------------------------------------------------------------- LDS-ring wave tiles
+// The tiles and lane layout of tile_dpp, with both operands of an entry copied
+// from global memory straight into a per-wave LDS ring of D entries by
+// asynchronous LDS-DMA loads (4 bytes per lane, contiguous in lane order).
+// Data in flight occupies no VGPRs, so D - 1 entries are fetched ahead of the
+// multiply.  Every block of every entry is copied by the same number of DMA
+// instructions, reading the zero block for an absent A_{i_a k} or B_kj, so the
+// number of loads issued after an entry is known and one s_waitcnt per entry
+// (vmcnt at most that number, clamped to the counter's 63) orders it before
+// its LDS reads.  Block slot indices come through the scalar cache, so no
+// other vector loads share the vmcnt counter in the loop.
+template <int B, int G> struct RingEntry {
+    static constexpr int kBlocks = G + 64 / B;               // A rows, then B columns
+    static constexpr int kBytes = kBlocks * B * B * 8;
+    static constexpr int kDwords = 2 * B * B;                // per block
+    static constexpr int kInstPerBlock = (kDwords + 63) / 64;
+    static constexpr int kInst = kBlocks * kInstPerBlock;    // DMA loads per entry
+};
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(3))) char lds_char_t;
+typedef const __attribute__((address_space(3))) double lds_cdouble_t;
+
+// s_waitcnt with vmcnt <= vm (expcnt and lgkmcnt not waited on)
+template <int VM> __device__ inline void wait_vmcnt()
+{
+    static_assert(VM >= 0 && VM <= 63, "vmcnt is 6 bits");
+    __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Instruction I of a block's DMA copies dwords 64 I + lane (the last one only
+// for the lanes inside the block); the immediate offset 256 I moves both the
+// global and the LDS address.
+template <int IPB, int DW, int... I>
+__device__ inline void dma_block(const char *g, lds_void_t *l, int lane, std::integer_sequence<int, I...>)
+{
+    ((I < IPB - 1 || 64 * I + lane < DW ? __builtin_amdgcn_global_load_lds((const void *)g, l, 4, 256 * I, 0)
+                                        : (void)0),
+     ...);
+}
+
+template <int B, int G, int D>
+__device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
+                                 const int *__restrict__ ent, const double *__restrict__ vA,
+                                 const double *__restrict__ vB, const double *__restrict__ zblk,
+                                 double *__restrict__ vC, double alpha, double beta, lds_char_t *ring)
+{
+    using RE = RingEntry<B, G>;
+    constexpr int JT = 64 / B;
+    constexpr int BB = B * B;
+    constexpr int NA = (BB + 15) / 16;
+    constexpr int HS = G + G * JT;
+    constexpr int ES = G + JT;
+    constexpr int NB = RE::kBlocks, DW = RE::kDwords, IPB = RE::kInstPerBlock, NI = RE::kInst;
+    const int lane = threadIdx.x & 63;
+    const int l16 = lane & 15;
+    const int jl0 = lane / B, c = lane - jl0 * B;
+    const bool lane_ok = jl0 < JT;
+    const int jl = lane_ok ? jl0 : JT - 1;
+    const int *h = hdr + tile * HS;
+    int cs[G];
+    bool cact[G];
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        cs[a] = lane_ok ? h[G + a * JT + jl] : -1;
+        cact[a] = cs[a] >= 0;
+    }
+    double acc[G][B];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int r = 0; r < B; ++r) acc[a][r] = 0.0;
+
+    const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
+    const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
+    const int n = (int)(e1 - e0);
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
+
+    // Copy entry q (< n) into ring position P; keep its A slots in `asl`.  The
+    // DMA's immediate offset advances the global and the LDS address together.
+    const int lane4 = 4 * lane;
+    auto issue = [&](auto P, int q, int (&asl)[G]) {
+        lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
+        int sl[NB];
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) sl[blk] = entu[(int64_t)q * ES + blk];
+#pragma unroll
+        for (int a = 0; a < G; ++a) asl[a] = sl[a];
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) {
+            const double *src = sl[blk] >= 0 ? (blk < G ? vA : vB) + (int64_t)sl[blk] * BB : zblk;
+            const char *g = reinterpret_cast<const char *>(src) + lane4;
+            lds_void_t *l = (lds_void_t *)(slot + blk * (BB * 8));
+            dma_block<IPB, DW>(g, l, lane, std::make_integer_sequence<int, IPB>{});
+        }
+    };
+    // wait until at most `later` entries' loads are outstanding
+    auto wait_for = [&](int later) {
+        if (later >= 2) wait_vmcnt<(2 * NI < 63 ? 2 * NI : 63)>();
+        else if (later == 1) wait_vmcnt<(NI < 63 ? NI : 63)>();
+        else wait_vmcnt<0>();
+    };
+    // multiply the entry held at ring position P
+    auto compute = [&](auto P, const int (&as)[G]) {
+        const lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
+        double xa[G][NA], bv[B];
+#pragma unroll
+        for (int a = 0; a < G; ++a) {
+            if (as[a] < 0) continue;
+            lds_cdouble_t *ap = (lds_cdouble_t *)(slot + a * (BB * 8));
+#pragma unroll
+            for (int v = 0; v < NA; ++v) {
+                int idx = l16 + 16 * v;
+                if (idx >= BB) idx -= BB;
+                xa[a][v] = ap[idx];
+            }
+        }
+        lds_cdouble_t *bp = (lds_cdouble_t *)(slot + (G + jl) * (BB * 8)) + c;
+#pragma unroll
+        for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
+        dpp_entry<B, G, NA>(as, xa, bv, acc);
+    };
+    static_assert(D >= 2 && D <= 3, "ring depth 2 or 3");
+
+    int asl[D][G];
+    if (0 < n) issue(std::integral_constant<int, 0>{}, 0, asl[0]);
+    if (D == 3 && 1 < n) issue(std::integral_constant<int, 1 % D>{}, 1, asl[1 % D]);
+    for (int q0 = 0; q0 < n; q0 += D) {
+        // ring position of entry q0 + r is r; entry q0 + r + D - 1 goes to (r + D - 1) % D
+        auto step = [&](auto R) {
+            constexpr int r = decltype(R)::value;
+            const int q = q0 + r;
+            if (q >= n) return;
+            if (q + D - 1 < n) issue(std::integral_constant<int, (r + D - 1) % D>{}, q + D - 1, asl[(r + D - 1) % D]);
+            wait_for(min(D - 1, n - 1 - q));
+            compute(std::integral_constant<int, r>{}, asl[r]);
+        };
+        step(std::integral_constant<int, 0>{});
+        step(std::integral_constant<int, 1>{});
+        if constexpr (D == 3) step(std::integral_constant<int, 2>{});
+    }
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        if (!cact[a]) continue;
+        double *cp = vC + (int64_t)cs[a] * BB + c;
+        if (beta == 0.0) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
+        }
+    }
+}
+
 }  // namespace bsm
