@@ -86,11 +86,13 @@ def product_mode(args):
         log(f"[product] launch {k}")
     st = ctx.product_stats()[0]
     src = torch.empty(1 << 28, dtype=torch.float64, device=ctx.device).fill_(1.0)   # 2 GiB
+    log(f"[product] kernel {kernel_name(st)}, sources {kernel_sources_sha()}")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     ms = st["ms"] / st["launches"]
-    print(json.dumps({"mode": "product", "flops_per_launch": flops, "avg_ms": ms,
+    print(json.dumps({"mode": "product", "kernel": kernel_name(st), "sources_sha256_16": kernel_sources_sha(),
+                      "flops_per_launch": flops, "avg_ms": ms,
                       "tflops": flops / (ms * 1e-3) / 1e12, "blocks": P.nnzb,
                       "algorithmic_bytes": 3 * P.nnzb * b * b * 8, "copy_bytes": 2 * src.numel() * 8}),
           flush=True)
@@ -301,15 +303,31 @@ def cpu_baseline(args):
                       f"{flops / 1e9:.1f} GFLOP in {dt:.1f} s"}
 
 
-def measured_traffic(kernel_src: str):
-    """HBM bytes per launch of the dominant kernel from the committed counter summary,
-    or None when the kernel source has changed since the counters were taken."""
+KERNEL_SOURCES = ("paper_2205_08941_amd/csrc/product.hip", "paper_2205_08941_amd/csrc/tiles.h")
+
+
+def kernel_sources_sha() -> str:
+    """First 16 hex digits of the SHA-256 of the product kernels' sources."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_product_f64_dpp_si4096_b9_traffic.json")
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def kernel_name(st) -> str:
+    b, g, v = st["b"], st["rows"], st["variant"]
+    return {0: f"k_product_sgpr<{b}, {g}>", 1: f"k_product_f64_dpp<{b}, {g}>", 2: f"k_product_wg<{b}>",
+            3: f"k_product_ring<{b}, {g}, 3>", 4: f"k_product_ring<{b}, {g}, 2>"}.get(v, f"variant {v}")
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary
+    profiles/<name>, or None when the kernel sources have changed since the counters
+    were taken."""
     try:
-        d = json.load(open(path))
-        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()[:16]
-        if d.get("source_sha256_16") != sha:
+        d = json.load(open(os.path.join(ROOT, "profiles", name)))
+        if d.get("sources_sha256_16") != kernel_sources_sha():
             return None
         return d["hbm_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
@@ -433,19 +451,19 @@ def main():
         "pattern_build_s": round(pattern_s, 3),
         "roofline": {
             "bound": "alu",
-            "kernel": f"k_product_f64<{s.b}> P{top['cutoffs'][0]:g} x P{top['cutoffs'][1]:g} -> "
+            "kernel": f"{kernel_name(top)}: P{top['cutoffs'][0]:g} x P{top['cutoffs'][1]:g} -> "
                       f"P{top['cutoffs'][2]:g}",
             "achieved": round(achieved, 3),
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": measured_traffic("paper_2205_08941_amd/csrc/product.hip") if s.b == 9 else None,
+            "traffic": measured_traffic(f"k_product_si4096_b9_traffic.json") if s.b == 9 else None,
             "avg_launch_ms": round(avg_ms, 3),
             "launches": top["launches"],
             "flops_per_launch": per_launch_flops,
         },
         "product_classes": [
-            {"cutoffs": st["cutoffs"], "launches": st["launches"],
+            {"cutoffs": st["cutoffs"], "kernel": kernel_name(st), "launches": st["launches"],
              "tflops": round(st["flops"] / (st["ms"] * 1e-3) / 1e12, 3), "ms": round(st["ms"], 2)}
             for st in stats],
     }

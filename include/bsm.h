@@ -106,13 +106,16 @@ const char *bsm_last_error(void);
 
 /* Per-class timing of block products: with profiling on, every product launch
  * (from any entry point, drivers included) is bracketed by HIP events on the
- * context's stream.  Classes are (P_A, P_B, P_C) triples. */
+ * context's stream.  Classes are (P_A, P_B, P_C) triples with the kernel
+ * variant, rows per tile and operand precision of the launches. */
 typedef struct {
     int natoms, b;
     double cutoff_a, cutoff_b, cutoff_c;  /* Angstrom */
     int64_t launches;
     double flops;        /* algorithmic flops summed over the launches */
     double ms;           /* summed event time, milliseconds */
+    int variant, rows;   /* kernel variant (bsm_ctx_set_product_variant) and rows per tile */
+    int precision;       /* BSM_F64, BSM_F32 or BSM_BF16 */
 } bsm_product_stat;
 
 /* Rows of C per wavefront tile in product plans built from now on: 2, 4 or 8

@@ -91,7 +91,8 @@ class _GuessResult(ctypes.Structure):
 
 class _ProductStat(ctypes.Structure):
     _fields_ = [("natoms", c_int), ("b", c_int), ("cutoff_a", c_double), ("cutoff_b", c_double),
-                ("cutoff_c", c_double), ("launches", c_int64), ("flops", c_double), ("ms", c_double)]
+                ("cutoff_c", c_double), ("launches", c_int64), ("flops", c_double), ("ms", c_double),
+                ("variant", c_int), ("rows", c_int), ("precision", c_int)]
 
 
 class _LNVParams(ctypes.Structure):
@@ -261,7 +262,8 @@ class Context:
         arr = (_ProductStat * max(n.value, 1))()
         _check(_lib.bsm_ctx_product_stats(self.handle, arr, n.value, ctypes.byref(n)))
         return [dict(natoms=a.natoms, b=a.b, cutoffs=(a.cutoff_a, a.cutoff_b, a.cutoff_c),
-                     launches=a.launches, flops=a.flops, ms=a.ms) for a in arr[: n.value]]
+                     launches=a.launches, flops=a.flops, ms=a.ms, variant=a.variant, rows=a.rows,
+                     precision=a.precision) for a in arr[: n.value]]
 
     def _alloc(self, nbytes, user):
         try:

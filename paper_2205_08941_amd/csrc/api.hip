@@ -83,8 +83,7 @@ void Context::retire_profile(const std::function<bool(const Plan *)> &pick)
             if (pick(r.plan)) {
                 float ms = 0.f;
                 (void)hipEventElapsedTime(&ms, r.start, r.stop);
-                auto &acc = retired[std::make_tuple(r.plan->natoms, r.plan->b, r.plan->cutoffs[0],
-                                                    r.plan->cutoffs[1], r.plan->cutoffs[2])];
+                auto &acc = retired[prof_key(r)];
                 acc.launches += 1;
                 acc.flops += r.plan->flops;
                 acc.ms += ms;
@@ -281,8 +280,7 @@ int bsm_ctx_product_stats(bsm_ctx ctx, bsm_product_stat *out, int max, int *coun
     for (auto &r : c.prof) {
         float ms = 0.f;
         BSM_HIP_TRY(hipEventElapsedTime(&ms, r.start, r.stop));
-        auto &acc = agg[std::make_tuple(r.plan->natoms, r.plan->b, r.plan->cutoffs[0], r.plan->cutoffs[1],
-                                        r.plan->cutoffs[2])];
+        auto &acc = agg[Context::prof_key(r)];
         acc.launches += 1;
         acc.flops += r.plan->flops;
         acc.ms += ms;
@@ -295,6 +293,9 @@ int bsm_ctx_product_stats(bsm_ctx ctx, bsm_product_stat *out, int max, int *coun
         s.cutoff_a = std::get<2>(kv.first);
         s.cutoff_b = std::get<3>(kv.first);
         s.cutoff_c = std::get<4>(kv.first);
+        s.variant = std::get<5>(kv.first);
+        s.rows = std::get<6>(kv.first);
+        s.precision = std::get<7>(kv.first);
         s.launches = kv.second.launches;
         s.flops = kv.second.flops;
         s.ms = kv.second.ms;

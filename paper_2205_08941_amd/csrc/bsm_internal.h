@@ -97,7 +97,15 @@ class Context {
     struct ProfRec {
         const Plan *plan;
         hipEvent_t start, stop;
+        int prec;               // BSM_F64, BSM_F32 or BSM_BF16
     };
+    // statistics class: (natoms, b, cutoffs A, B, C, kernel variant, rows per tile, precision)
+    using ProfKey = std::tuple<int, int, double, double, double, int, int, int>;
+    static ProfKey prof_key(const ProfRec &r)
+    {
+        return ProfKey(r.plan->natoms, r.plan->b, r.plan->cutoffs[0], r.plan->cutoffs[1], r.plan->cutoffs[2],
+                       r.plan->variant, r.plan->G, r.prec);
+    }
     bool profiling = false;
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> event_pool;
@@ -106,7 +114,7 @@ class Context {
         double flops = 0.0, ms = 0.0;
     };
     // launches of plans whose patterns were destroyed while profiling
-    std::map<std::tuple<int, int, double, double, double>, ProfAcc> retired;
+    std::map<ProfKey, ProfAcc> retired;
     // FP32 operand copies for mixed-precision products (grown on demand)
     DevBuf f32buf[2];
     float *scratch_f32(int which, int64_t n);

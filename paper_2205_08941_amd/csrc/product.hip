@@ -492,7 +492,7 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
     (void)PB;
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
-    Context::ProfRec rec{plan, nullptr, nullptr};
+    Context::ProfRec rec{plan, nullptr, nullptr, BSM_F64};
     if (ctx->profiling) {
         rec.start = ctx->take_event();
         rec.stop = ctx->take_event();
@@ -529,7 +529,7 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     const int bf = prec == BSM_BF16 ? 1 : 0;
     k_round_copy<<<(unsigned)((na + 255) / 256), 256, 0, st>>>(na, A, a32, bf);
     k_round_copy<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, Bm, b32, bf);
-    Context::ProfRec rec{plan, nullptr, nullptr};
+    Context::ProfRec rec{plan, nullptr, nullptr, prec};
     if (ctx->profiling) {
         rec.start = ctx->take_event();
         rec.stop = ctx->take_event();
