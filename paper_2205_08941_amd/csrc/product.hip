@@ -84,17 +84,16 @@ __global__ __launch_bounds__(256) void k_product_wg(
 }
 
 // One wave tile per one-wave workgroup, operands through a per-wave LDS ring.
-template <int B, int G, int D>
+template <int B, int G, int D, class T = double>
 __global__ __launch_bounds__(64) void k_product_ring(
     int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
-    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
-    const double *__restrict__ vB, const double *__restrict__ zblk, double *__restrict__ vC, double alpha,
-    double beta)
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const T *__restrict__ vA,
+    const T *__restrict__ vB, const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta)
 {
-    __shared__ __attribute__((aligned(16))) char ring[D * RingEntry<B, G>::kBytes];
+    __shared__ __attribute__((aligned(16))) char ring[D * RingEntry<B, G, T>::kBytes];
     const int64_t t = logical_workgroup(nwg_padded);
     if (t >= ntiles) return;
-    tile_ring<B, G, D>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta, (lds_char_t *)ring);
+    tile_ring<B, G, D, T>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta, (lds_char_t *)ring);
 }
 
 // ---------------------------------------------------------------- operand rounding
@@ -336,14 +335,14 @@ void launch_wg(hipStream_t st, const Plan *plan, const double *A, const double *
                                                          plan->ent.as<int>(), A, Bm, C, alpha, beta);
 }
 
-template <int B, int G, int D>
-void launch_ring(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
-                 double beta, const double *zblk)
+template <int B, int G, int D, class T = double>
+void launch_ring(hipStream_t st, const Plan *plan, const T *A, const T *Bm, double *C, double alpha, double beta,
+                 const T *zblk)
 {
     const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
-    k_product_ring<B, G, D><<<(unsigned)nwg_padded, 64, 0, st>>>(plan->ntiles, nwg_padded, plan->order.as<int>(),
-                                                                plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
-                                                                plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta);
+    k_product_ring<B, G, D, T><<<(unsigned)nwg_padded, 64, 0, st>>>(
+        plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+        plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta);
 }
 
 template <int B>
@@ -383,8 +382,17 @@ void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *B
 
 template <int B>
 void launch_b32(hipStream_t st, const Plan *plan, const float *A, const float *Bm, double *C, double alpha,
-                double beta)
+                double beta, const float *zblk)
 {
+    if constexpr (B == 9 || B == 4) {
+        if (plan->variant == 3 || plan->variant == 4) {   // LDS ring, FP32 operands
+            switch (plan->G) {
+                case 2: launch_ring<B, 2, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                case 4: launch_ring<B, 4, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                default: break;
+            }
+        }
+    }
     switch (plan->G) {
         case 2: launch_bg<B, 2, float>(st, plan, A, Bm, C, alpha, beta); break;
         case 4: launch_bg<B, 4, float>(st, plan, A, Bm, C, alpha, beta); break;
@@ -537,7 +545,7 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     }
     switch (PC->b) {
 #define X(b) \
-    case b: launch_b32<b>(st, plan, a32, b32, C, alpha, beta); break;
+    case b: launch_b32<b>(st, plan, a32, b32, C, alpha, beta, ctx->zero_block.as<float>()); break;
         BSM_FOR_EACH_B(X)
 #undef X
         default: throw Error{BSM_EINVAL, "b must be in 1..16"};

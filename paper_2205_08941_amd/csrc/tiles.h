@@ -138,9 +138,9 @@ __device__ inline void tile_sgpr(int64_t tile, const int *__restrict__ hdr, cons
 // track that hazard into inline asm.
 #define BSM_FMA_DPP(acc, a, bq, lane) "v_fmac_f64_dpp " acc ", " a ", " bq " row_newbcast:" lane " row_mask:0xf bank_mask:0xf\n"
 
-template <int B, int NA, int R> struct DppRow;
+template <int B, int NA, int R, class T = double> struct DppRow;
 
-template <int NA, int R> struct DppRow<9, NA, R> {
+template <int NA, int R> struct DppRow<9, NA, R, double> {
     static constexpr int e(int m) { return R * 9 + m; }
     __device__ static inline void run(double &acc, const double (&av)[NA], const double (&bv)[9])
     {
@@ -161,7 +161,7 @@ template <int NA, int R> struct DppRow<9, NA, R> {
     }
 };
 
-template <int NA, int R> struct DppRow<4, NA, R> {
+template <int NA, int R> struct DppRow<4, NA, R, double> {
     static constexpr int e(int m) { return R * 4 + m; }
     __device__ static inline void run(double &acc, const double (&av)[NA], const double (&bv)[4])
     {
@@ -176,11 +176,50 @@ template <int NA, int R> struct DppRow<4, NA, R> {
 };
 #undef BSM_FMA_DPP
 
-template <int B, int NA, int... R>
-__device__ inline void fma_block(double (&acc)[B], const double (&av)[NA], const double (&bv)[B],
-                                 std::integer_sequence<int, R...>)
+// FP32 operands and accumulators: the same rows with v_fmac_f32_dpp (one FP32
+// fused multiply-add per element, in m order, as the FP32 reference sums).
+#define BSM_FMA_DPP32(acc, a, bq, lane) "v_fmac_f32_dpp " acc ", " a ", " bq " row_newbcast:" lane " row_mask:0xf bank_mask:0xf\n"
+
+template <int NA, int R> struct DppRow<9, NA, R, float> {
+    static constexpr int e(int m) { return R * 9 + m; }
+    __device__ static inline void run(float &acc, const float (&av)[NA], const float (&bv)[9])
+    {
+        asm("s_nop 1\n"
+            BSM_FMA_DPP32("%0", "%1", "%10", "%19") BSM_FMA_DPP32("%0", "%2", "%11", "%20")
+            BSM_FMA_DPP32("%0", "%3", "%12", "%21") BSM_FMA_DPP32("%0", "%4", "%13", "%22")
+            BSM_FMA_DPP32("%0", "%5", "%14", "%23") BSM_FMA_DPP32("%0", "%6", "%15", "%24")
+            BSM_FMA_DPP32("%0", "%7", "%16", "%25") BSM_FMA_DPP32("%0", "%8", "%17", "%26")
+            BSM_FMA_DPP32("%0", "%9", "%18", "%27")
+            : "+v"(acc)
+            : "v"(av[e(0) >> 4]), "v"(av[e(1) >> 4]), "v"(av[e(2) >> 4]), "v"(av[e(3) >> 4]),
+              "v"(av[e(4) >> 4]), "v"(av[e(5) >> 4]), "v"(av[e(6) >> 4]), "v"(av[e(7) >> 4]),
+              "v"(av[e(8) >> 4]),
+              "v"(bv[0]), "v"(bv[1]), "v"(bv[2]), "v"(bv[3]), "v"(bv[4]), "v"(bv[5]), "v"(bv[6]), "v"(bv[7]),
+              "v"(bv[8]),
+              "n"(e(0) & 15), "n"(e(1) & 15), "n"(e(2) & 15), "n"(e(3) & 15), "n"(e(4) & 15), "n"(e(5) & 15),
+              "n"(e(6) & 15), "n"(e(7) & 15), "n"(e(8) & 15));
+    }
+};
+
+template <int NA, int R> struct DppRow<4, NA, R, float> {
+    static constexpr int e(int m) { return R * 4 + m; }
+    __device__ static inline void run(float &acc, const float (&av)[NA], const float (&bv)[4])
+    {
+        asm("s_nop 1\n"
+            BSM_FMA_DPP32("%0", "%1", "%5", "%9") BSM_FMA_DPP32("%0", "%2", "%6", "%10")
+            BSM_FMA_DPP32("%0", "%3", "%7", "%11") BSM_FMA_DPP32("%0", "%4", "%8", "%12")
+            : "+v"(acc)
+            : "v"(av[e(0) >> 4]), "v"(av[e(1) >> 4]), "v"(av[e(2) >> 4]), "v"(av[e(3) >> 4]),
+              "v"(bv[0]), "v"(bv[1]), "v"(bv[2]), "v"(bv[3]),
+              "n"(e(0) & 15), "n"(e(1) & 15), "n"(e(2) & 15), "n"(e(3) & 15));
+    }
+};
+#undef BSM_FMA_DPP32
+
+template <int B, int NA, class T, int... R>
+__device__ inline void fma_block(T (&acc)[B], const T (&av)[NA], const T (&bv)[B], std::integer_sequence<int, R...>)
 {
-    (DppRow<B, NA, R>::run(acc[R], av, bv), ...);
+    (DppRow<B, NA, R, T>::run(acc[R], av, bv), ...);
 }
 
 // Element l16 + 16 v of the block into register v; indices past the block wrap
@@ -211,14 +250,13 @@ __device__ inline void load_b(double (&bv)[B], const double *__restrict__ vBc, c
     for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
 }
 
-template <int B, int G, int NA>
-__device__ inline void dpp_entry(const int (&as)[G], const double (&av)[G][NA], const double (&bv)[B],
-                                 double (&acc)[G][B])
+template <int B, int G, int NA, class T = double>
+__device__ inline void dpp_entry(const int (&as)[G], const T (&av)[G][NA], const T (&bv)[B], T (&acc)[G][B])
 {
 #pragma unroll
     for (int a = 0; a < G; ++a) {
         if (as[a] < 0) continue;   // wave-uniform
-        fma_block<B, NA>(acc[a], av[a], bv, std::make_integer_sequence<int, B>{});
+        fma_block<B, NA, T>(acc[a], av[a], bv, std::make_integer_sequence<int, B>{});
     }
 }
 
@@ -463,17 +501,17 @@ __device__ inline void tile_wg(int64_t tile, const int *__restrict__ hdr, const 
 // (vmcnt at most that number, clamped to the counter's 63) orders it before
 // its LDS reads.  Block slot indices come through the scalar cache, so no
 // other vector loads share the vmcnt counter in the loop.
-template <int B, int G> struct RingEntry {
+template <int B, int G, class T = double> struct RingEntry {
     static constexpr int kBlocks = G + 64 / B;               // A rows, then B columns
-    static constexpr int kBytes = kBlocks * B * B * 8;
-    static constexpr int kDwords = 2 * B * B;                // per block
+    static constexpr int kBytes = kBlocks * B * B * (int)sizeof(T);
+    static constexpr int kDwords = B * B * (int)sizeof(T) / 4;   // per block
     static constexpr int kInstPerBlock = (kDwords + 63) / 64;
     static constexpr int kInst = kBlocks * kInstPerBlock;    // DMA loads per entry
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(3))) char lds_char_t;
-typedef const __attribute__((address_space(3))) double lds_cdouble_t;
+template <class T> using lds_const_t = const __attribute__((address_space(3))) T;
 
 // s_waitcnt with vmcnt <= vm (expcnt and lgkmcnt not waited on)
 template <int VM> __device__ inline void wait_vmcnt()
@@ -493,13 +531,17 @@ __device__ inline void dma_block(const char *g, lds_void_t *l, int lane, std::in
      ...);
 }
 
-template <int B, int G, int D>
+// T = double: FP64 product.  T = float: operands already rounded (FP32, or BF16
+// stored as FP32), FP32 fused multiply-adds in the same (k, m) order, the sums
+// widened to FP64 for alpha, beta and the store.
+template <int B, int G, int D, class T = double>
 __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
-                                 const int *__restrict__ ent, const double *__restrict__ vA,
-                                 const double *__restrict__ vB, const double *__restrict__ zblk,
-                                 double *__restrict__ vC, double alpha, double beta, lds_char_t *ring)
+                                 const int *__restrict__ ent, const T *__restrict__ vA, const T *__restrict__ vB,
+                                 const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta,
+                                 lds_char_t *ring)
 {
-    using RE = RingEntry<B, G>;
+    using RE = RingEntry<B, G, T>;
+    constexpr int ESZ = (int)sizeof(T);
     constexpr int JT = 64 / B;
     constexpr int BB = B * B;
     constexpr int NA = (BB + 15) / 16;
@@ -519,11 +561,11 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
         cs[a] = lane_ok ? h[G + a * JT + jl] : -1;
         cact[a] = cs[a] >= 0;
     }
-    double acc[G][B];
+    T acc[G][B];
 #pragma unroll
     for (int a = 0; a < G; ++a)
 #pragma unroll
-        for (int r = 0; r < B; ++r) acc[a][r] = 0.0;
+        for (int r = 0; r < B; ++r) acc[a][r] = T(0);
 
     const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
                        ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
@@ -544,9 +586,9 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
         for (int a = 0; a < G; ++a) asl[a] = sl[a];
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) {
-            const double *src = sl[blk] >= 0 ? (blk < G ? vA : vB) + (int64_t)sl[blk] * BB : zblk;
+            const T *src = sl[blk] >= 0 ? (blk < G ? vA : vB) + (int64_t)sl[blk] * BB : zblk;
             const char *g = reinterpret_cast<const char *>(src) + lane4;
-            lds_void_t *l = (lds_void_t *)(slot + blk * (BB * 8));
+            lds_void_t *l = (lds_void_t *)(slot + blk * (BB * ESZ));
             dma_block<IPB, DW>(g, l, lane, std::make_integer_sequence<int, IPB>{});
         }
     };
@@ -559,11 +601,11 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
     // multiply the entry held at ring position P
     auto compute = [&](auto P, const int (&as)[G]) {
         const lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
-        double xa[G][NA], bv[B];
+        T xa[G][NA], bv[B];
 #pragma unroll
         for (int a = 0; a < G; ++a) {
             if (as[a] < 0) continue;
-            lds_cdouble_t *ap = (lds_cdouble_t *)(slot + a * (BB * 8));
+            lds_const_t<T> *ap = (lds_const_t<T> *)(slot + a * (BB * ESZ));
 #pragma unroll
             for (int v = 0; v < NA; ++v) {
                 int idx = l16 + 16 * v;
@@ -571,10 +613,10 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
                 xa[a][v] = ap[idx];
             }
         }
-        lds_cdouble_t *bp = (lds_cdouble_t *)(slot + (G + jl) * (BB * 8)) + c;
+        lds_const_t<T> *bp = (lds_const_t<T> *)(slot + (G + jl) * (BB * ESZ)) + c;
 #pragma unroll
         for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
-        dpp_entry<B, G, NA>(as, xa, bv, acc);
+        dpp_entry<B, G, NA, T>(as, xa, bv, acc);
     };
     static_assert(D >= 2 && D <= 3, "ring depth 2 or 3");
 
@@ -601,10 +643,10 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
         double *cp = vC + (int64_t)cs[a] * BB + c;
         if (beta == 0.0) {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
+            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r] + beta * cp[r * B];
         }
     }
 }
