@@ -5,8 +5,11 @@
 // mask(A_p B_p) + beta_p C_p), typically from independent systems of uneven
 // size and orbital count (b = 4 or 9).  Every product keeps its own plan; the
 // batch concatenates their tiles into one work list.  A fixed grid of
-// wavefronts stays resident and takes tiles from work queues by an atomic
-// counter until the list is exhausted (every wave reaches the exit test).
+// one-wave workgroups stays resident and takes tiles from work queues by an
+// atomic counter until the list is exhausted (every wave reaches the exit
+// test).  A tile runs the same device code as in the separate launches (the
+// LDS-ring tile for b = 9, the register-pipelined tiles for b = 4), in the
+// workgroup's own LDS ring.
 // Tiles write disjoint outputs, so the result does not depend on which wave
 // takes which tile: it equals the separate products bit for bit.
 //
@@ -20,12 +23,14 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 namespace bsm {
 
 // product kinds handled by the persistent kernel
-enum { kKindF64Dpp9 = 0, kKindF64Dpp4 = 1, kKindF32b9 = 2, kKindF32b4 = 3 };
+enum { kKindF64Ring9 = 0, kKindF64Dpp4 = 1, kKindF32Ring9 = 2, kKindF32b4 = 3 };
+constexpr int kBatchRing = 2;   // LDS ring depth of the b = 9 tiles
 
 struct BatchDesc {
     int kind;
@@ -48,13 +53,15 @@ __global__ void k_zero_counters(int n, unsigned *c)
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
 }
 
-// One kernel per batch precision (F64 = true: the DPP kinds; false: the FP32
-// kinds), so that each is compiled with the registers its own tiles need.
+// One kernel per batch precision (F64 = true: FP64 operands; false: FP32),
+// so that each is compiled with the registers its own tiles need.
 template <bool F64>
-__global__ __launch_bounds__(256) void k_product_batch(const BatchDesc *__restrict__ desc, const int2 *__restrict__ items,
-                                                       const int64_t *__restrict__ qbeg, int nq,
-                                                       unsigned *__restrict__ counters, const double *__restrict__ zblk)
+__global__ __launch_bounds__(64) void k_product_batch(const BatchDesc *__restrict__ desc, const int2 *__restrict__ items,
+                                                      const int64_t *__restrict__ qbeg, int nq,
+                                                      unsigned *__restrict__ counters, const double *__restrict__ zblk)
 {
+    using T = typename std::conditional<F64, double, float>::type;
+    __shared__ __attribute__((aligned(16))) char ring[kBatchRing * RingEntry<9, 4, T>::kBytes];
     const int lane = threadIdx.x & 63;
     const int q = (int)(blockIdx.x % (unsigned)nq);   // workgroups are dealt round-robin to the XCDs
     const int64_t base = qbeg[q];
@@ -69,16 +76,18 @@ __global__ __launch_bounds__(256) void k_product_batch(const BatchDesc *__restri
         const BatchDesc d = desc[p];
         const int kind = __builtin_amdgcn_readfirstlane(d.kind);
         if constexpr (F64) {
-            if (kind == kKindF64Dpp9)
-                tile_dpp<9, 4>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A, (const double *)d.B, zblk, d.C,
-                               d.alpha, d.beta);
+            if (kind == kKindF64Ring9)
+                tile_ring<9, 4, kBatchRing, double>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A,
+                                                    (const double *)d.B, zblk, d.C, d.alpha, d.beta,
+                                                    (lds_char_t *)ring);
             else
                 tile_dpp<4, 4>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A, (const double *)d.B, zblk, d.C,
                                d.alpha, d.beta);
         } else {
-            if (kind == kKindF32b9)
-                tile_sgpr<9, 4, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A, (const float *)d.B, d.C,
-                                       d.alpha, d.beta);
+            if (kind == kKindF32Ring9)
+                tile_ring<9, 4, kBatchRing, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A,
+                                                   (const float *)d.B, (const float *)zblk, d.C, d.alpha, d.beta,
+                                                   (lds_char_t *)ring);
             else
                 tile_sgpr<4, 4, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A, (const float *)d.B, d.C,
                                        d.alpha, d.beta);
@@ -206,12 +215,12 @@ void bsm_batch_s::run(const bsm_batch_config &cfg)
         }
     }
     k_zero_counters<<<1, 64, 0, st>>>(cfg.queues, counters.as<unsigned>());
-    const int blocks = kCUs * cfg.waves_per_cu / 4;
+    const int blocks = kCUs * cfg.waves_per_cu;   // one wave each
     if (prec == BSM_F64)
-        k_product_batch<true><<<blocks, 256, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(),
+        k_product_batch<true><<<blocks, 64, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(),
                                                       cfg.queues, counters.as<unsigned>(), c->zero_block.as<double>());
     else
-        k_product_batch<false><<<blocks, 256, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(),
+        k_product_batch<false><<<blocks, 64, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(),
                                                        cfg.queues, counters.as<unsigned>(), c->zero_block.as<double>());
     BSM_HIP_TRY(hipGetLastError());
 }
@@ -246,8 +255,8 @@ int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *
         check_same_shape(&A[p], &C[p]);
         const int b = C[p].pattern->b;
         BSM_REQUIRE(b == 4 || b == 9, BSM_EINVAL, "batched products support b = 4 and 9");
-        // wave tiles of 4 rows: DPP for FP64, SGPR for the rounded operands
-        Plan *plan = get_plan_kind(c, A[p].pattern, B[p].pattern, C[p].pattern, precision == BSM_F64 ? 1 : 0, 4);
+        // wave tiles of 4 rows (the plans the separate launches use by default)
+        Plan *plan = get_plan_kind(c, A[p].pattern, B[p].pattern, C[p].pattern, b == 9 ? 4 : 1, 4);
         bt->plans.push_back(plan);
         bt->pa.push_back(A[p].pattern);
         bt->pb.push_back(B[p].pattern);
@@ -273,11 +282,11 @@ int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *
         x.alpha = alpha[p];
         x.beta = beta[p];
         if (precision == BSM_F64) {
-            x.kind = b == 9 ? kKindF64Dpp9 : kKindF64Dpp4;
+            x.kind = b == 9 ? kKindF64Ring9 : kKindF64Dpp4;
             x.A = A[p].blocks;
             x.B = B[p].blocks;
         } else {
-            x.kind = b == 9 ? kKindF32b9 : kKindF32b4;
+            x.kind = b == 9 ? kKindF32Ring9 : kKindF32b4;
             bt->a32.emplace_back(c, sizeof(float) * (size_t)std::max<int64_t>(1, bt->a_n.back()));
             bt->b32.emplace_back(c, sizeof(float) * (size_t)std::max<int64_t>(1, bt->b_n.back()));
             x.A = bt->a32.back().ptr;
