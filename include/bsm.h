@@ -129,8 +129,8 @@ int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
  * of 16 rows (4 wavefronts of 4 rows sharing the tile's B blocks, staged in
  * LDS, A as in 1; b = 4 and 9, else 0); 3 and 4 = the wave tiles of 1 with
  * both operands copied into a per-wave LDS ring by asynchronous LDS-DMA loads,
- * 2 (3) or 1 (4) entries ahead (b = 4 and 9, rows 2 or 4, else 0); -1 =
- * default (4 for b = 9, 1 for b = 4, else 0).  Variants 1 and 2 multiply absent (k, j) blocks by zero instead of
+ * 2 (3) or 1 (4) entries ahead (b = 4 and 9, rows 2, 4 or 8, else 0); -1 =
+ * default (4 for b = 4 and 9, with 8 rows per tile for b = 4, else 0).  Variants 1 and 2 multiply absent (k, j) blocks by zero instead of
  * skipping them, so a non-finite block of A can make other blocks of its
  * output row non-finite.  Clears cached plans (a bsm_batch made before keeps
  * pointers to them: destroy batches first). */

@@ -357,6 +357,7 @@ void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *B
                              : launch_ring<B, 2, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
                 case 4: deep ? launch_ring<B, 4, 3>(st, plan, A, Bm, C, alpha, beta, zblk)
                              : launch_ring<B, 4, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                case 8: launch_ring<B, 8, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
                 default: break;
             }
         }
@@ -389,6 +390,7 @@ void launch_b32(hipStream_t st, const Plan *plan, const float *A, const float *B
             switch (plan->G) {
                 case 2: launch_ring<B, 2, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk); return;
                 case 4: launch_ring<B, 4, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                case 8: launch_ring<B, 8, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk); return;
                 default: break;
             }
         }
@@ -407,7 +409,7 @@ void launch_b32(hipStream_t st, const Plan *plan, const float *A, const float *B
 }  // namespace
 
 int default_rows_per_wave(int b) { return b >= 5 ? 4 : (b == 4 ? 4 : 2); }
-int default_variant(int b) { return b == 9 ? 4 : (b == 4 ? 1 : 0); }
+int default_variant(int b) { return (b == 9 || b == 4) ? 4 : 0; }
 
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
                 Plan *plan, int G)
@@ -583,7 +585,8 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
 {
     int variant = ctx->product_variant >= 0 ? ctx->product_variant : default_variant(C->b);
     if (variant >= 2 && C->b != 9 && C->b != 4) variant = 0;
-    const int G = variant == 2 ? kMaxRows : (ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b));
+    int G = variant == 2 ? kMaxRows : (ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b));
+    if (variant == 4 && C->b == 4 && ctx->rows_per_wave == 0) G = 8;   // measured best for the b = 4 ring
     return get_plan_kind(ctx, A, B, C, variant, G);
 }
 

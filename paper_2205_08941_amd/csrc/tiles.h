@@ -601,22 +601,36 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
     // multiply the entry held at ring position P
     auto compute = [&](auto P, const int (&as)[G]) {
         const lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
-        T xa[G][NA], bv[B];
+        T bv[B];
+        lds_const_t<T> *bp = (lds_const_t<T> *)(slot + (G + jl) * (BB * ESZ)) + c;
 #pragma unroll
-        for (int a = 0; a < G; ++a) {
-            if (as[a] < 0) continue;
+        for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
+        auto read_row = [&](T (&xr)[NA], int a) {
             lds_const_t<T> *ap = (lds_const_t<T> *)(slot + a * (BB * ESZ));
 #pragma unroll
             for (int v = 0; v < NA; ++v) {
                 int idx = l16 + 16 * v;
                 if (idx >= BB) idx -= BB;
-                xa[a][v] = ap[idx];
+                xr[v] = ap[idx];
+            }
+        };
+        if constexpr (G <= 4) {
+            // all rows' A values read up front (their LDS latency overlaps)
+            T xa[G][NA];
+#pragma unroll
+            for (int a = 0; a < G; ++a)
+                if (as[a] >= 0) read_row(xa[a], a);
+            dpp_entry<B, G, NA, T>(as, xa, bv, acc);
+        } else {
+            // row by row, so that only one row of A is live next to 8 rows of sums
+#pragma unroll
+            for (int a = 0; a < G; ++a) {
+                if (as[a] < 0) continue;
+                T xr[NA];
+                read_row(xr, a);
+                fma_block<B, NA, T>(acc[a], xr, bv, std::make_integer_sequence<int, B>{});
             }
         }
-        lds_const_t<T> *bp = (lds_const_t<T> *)(slot + (G + jl) * (BB * ESZ)) + c;
-#pragma unroll
-        for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
-        dpp_entry<B, G, NA, T>(as, xa, bv, acc);
     };
     static_assert(D >= 2 && D <= 3, "ring depth 2 or 3");
 

@@ -132,7 +132,7 @@ def test_product_parity(bsm, ctx, b):
 @pytest.mark.parametrize("variant,rows,system", [(0, 2, "si256_disp"), (0, 4, "si256_disp"), (0, 8, "si256_disp"),
                                                   (1, 2, "si256_disp"), (1, 4, "si256_disp"), (2, 0, "si256_disp"),
                                                   (2, 0, "si216_disp"), (3, 4, "si256_disp"), (3, 2, "si216_disp"),
-                                                  (4, 4, "si216_disp"), (4, 2, "si256_disp")])
+                                                  (4, 4, "si216_disp"), (4, 2, "si256_disp"), (4, 8, "si216_disp")])
 @pytest.mark.parametrize("b", [4, 9])
 def test_product_kernel_variants(bsm, b, variant, rows, system):
     """Every product kernel variant and rows-per-wave choice gives the oracle's result
