@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=-1,
                     help="product kernel variant for --mode product (-1: the library default)")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="rows per tile for --mode product (0: the library default)")
     ap.add_argument("--mode", default="solve", choices=["solve", "product"],
                     help="product: only the dominant 16 A x 16 A -> 16 A product, --steps launches, plus a "
                          "2 GiB device copy (for hardware-counter runs and their byte calibration)")
@@ -72,6 +74,7 @@ def product_mode(args):
     rx = s.cutoffs["L"] + s.cutoffs["S"]
     ctx = bsm.Context(0)
     ctx.set_product_variant(args.variant)
+    ctx.set_rows_per_wave(args.rows)
     pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
     P = bsm.Pattern(ctx, pos, s.box, rx, b)
     g = torch.Generator(device=ctx.device)

@@ -156,6 +156,44 @@ def test_product_kernel_variants(bsm, b, variant, rows, system):
     ctx.close()
 
 
+@pytest.mark.parametrize("variant,rows", [(1, 4), (4, 4), (4, 8), (4, 2), (2, 0)])
+@pytest.mark.parametrize("b", [4, 9])
+def test_product_degenerate_cases(bsm, b, variant, rows):
+    """One atom (one tile, one entry padded to two); diagonal-only operands into a
+    wide output pattern (most tiles have no entries and only apply beta)."""
+    ctx = bsm.Context(0)
+    ctx.set_product_variant(variant)
+    ctx.set_rows_per_wave(rows)
+    say(f"degenerate products variant={variant} rows={rows} b={b}")
+    one = np.array([[1.0, 2.0, 3.0]])
+    P1 = gpat(bsm, ctx, one, (5.0, 5.0, 5.0), 2.0, b)
+    a = synth.random_blocks(1, b, 5)
+    bb = synth.random_blocks(1, b, 6)
+    c0 = synth.random_blocks(1, b, 7)
+    C = gmat(bsm, P1, c0)
+    bsm.multiply_truncate(2.0, gmat(bsm, P1, a), gmat(bsm, P1, bb), 0.5, C)
+    assert rel_err(host(C), 2.0 * a @ bb + 0.5 * c0) < 1e-14
+    s = SYSTEMS["si216_disp"]()
+    gd, g6 = gpat(bsm, ctx, s.positions, s.box, 1.0, b), gpat(bsm, ctx, s.positions, s.box, 6.0, b)
+    od, o6 = O.create_pattern(s.positions, s.box, 1.0), O.create_pattern(s.positions, s.box, 6.0)
+    assert od.nnz == len(s.positions)
+    a = synth.random_blocks(od.nnz, b, 8)
+    bb = synth.random_blocks(od.nnz, b, 9)
+    c0 = synth.random_blocks(o6.nnz, b, 10)
+    C = gmat(bsm, g6, c0)
+    bsm.multiply_truncate(1.5, gmat(bsm, gd, a), gmat(bsm, gd, bb), -0.25, C)
+    Co = O.Matrix(o6, b, c0.copy())
+    O.multiply_truncate(1.5, O.Matrix(od, b, a), O.Matrix(od, b, bb), -0.25, Co)
+    assert rel_err(host(C), Co.blocks) < 1e-13
+    # and the FP32 path on the same degenerate product
+    C = gmat(bsm, g6, c0)
+    bsm.multiply_truncate_prec(bsm.F32, 1.5, gmat(bsm, gd, a), gmat(bsm, gd, bb), -0.25, C)
+    Co = O.Matrix(o6, b, c0.copy())
+    O.multiply_truncate_mixed(1, 1.5, O.Matrix(od, b, a), O.Matrix(od, b, bb), -0.25, Co)
+    assert rel_err(host(C), Co.blocks) < 1e-14
+    ctx.close()
+
+
 def test_product_beta_zero_ignores_nan_and_is_deterministic(bsm, ctx):
     s = SYSTEMS["si64"]()
     P6, P8 = (gpat(bsm, ctx, s.positions, s.box, r, 4) for r in (6.0, 8.0))
