@@ -207,7 +207,8 @@ def _solver(ctx, s):
 
 
 def mixed_mode(args):
-    """Time to the converged energy: FP64 products against BF16 -> FP32 -> 3 x FP64 stages."""
+    """Time to the converged energy: FP64 products against BF16 -> FP32 -> 3 x FP64 stages
+    (and BF16 -> 5 x FP64)."""
     import torch
     import synth
     import paper_2205_08941_amd as bsm
@@ -216,9 +217,12 @@ def mixed_mode(args):
     P, S, H, Z, L = _solver(ctx, s)
     bsm.hotelling_inverse(S, Z, max_iter=100, tol=1e-12)
     lnv = bsm.LNV(S, H, Z, L, s.n_electrons, tol_E=args.tol_e, init_from_z=True)
-    stages = [(bsm.BF16, 30, 0.0, True), (bsm.F32, 60, 1e-6, True), (bsm.F64, 3, 0.0, False)]
+    # BF16 products until the energy stops falling, FP32 to |dE| < 1e-4 Ha, then 3 FP64 steps; and the
+    # shortest schedule measured to stay within 1e-6 Ha/atom: BF16, then 5 FP64 steps
+    stages = [(bsm.BF16, 30, 0.0, True), (bsm.F32, 60, 1e-4, True), (bsm.F64, 3, 0.0, False)]
+    short = [(bsm.BF16, 30, 0.0, True), (bsm.F64, 5, 0.0, False)]
     out = {}
-    for tag, sched in (("f64", [(bsm.F64, args.max_lnv, args.tol_e, False)]), ("mixed", stages)):
+    for tag, sched in (("f64", [(bsm.F64, args.max_lnv, args.tol_e, False)]), ("mixed", stages), ("bf16_f64x5", short)):
         for rep in range(args.warmup + 1):
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -232,13 +236,17 @@ def mixed_mode(args):
                         status=r["status"], idempotency_error=e_idem, hotelling=hr.iterations)
         log(f"[mixed] {tag}: {dt:.2f} s, iterations {r['iterations']}, E {r['E']:.10f}, e_idem {e_idem:.3e}")
     dE = abs(out["mixed"]["E"] - out["f64"]["E"]) / s.natoms
+    out["bf16_f64x5"]["dE_per_atom_Ha"] = abs(out["bf16_f64x5"]["E"] - out["f64"]["E"]) / s.natoms
     res = {"metric": "s per converged LNV solve, 4096-atom 9-orb, mixed-precision products",
            "value": out["mixed"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
            "ms_per_step": out["mixed"]["seconds"] * 1e3, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "bf16/f32 products, f64 traces", "data": "synthetic",
-           "config": {"workload": "si4096_b9: Hotelling + LNV, BF16 (30) -> FP32 (60, 1e-6 Ha) -> 3 FP64 steps"},
+           "config": {"workload": "si4096_b9: Hotelling + LNV, BF16 (matrix cores, until E rises) -> FP32 "
+                                  "(to |dE| < 1e-4 Ha) -> 3 FP64 steps"},
            "f64": out["f64"], "mixed": out["mixed"], "dE_per_atom_Ha": dE,
-           "speedup_vs_f64": round(out["f64"]["seconds"] / out["mixed"]["seconds"], 3)}
+           "speedup_vs_f64": round(out["f64"]["seconds"] / out["mixed"]["seconds"], 3),
+           "bf16_f64x5": out["bf16_f64x5"],
+           "bf16_f64x5_speedup_vs_f64": round(out["f64"]["seconds"] / out["bf16_f64x5"]["seconds"], 3)}
     print(json.dumps(res), flush=True)
 
 

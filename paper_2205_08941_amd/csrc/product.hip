@@ -120,6 +120,37 @@ __global__ void k_round_copy(int64_t n, const double *__restrict__ x, float *__r
     y[e] = bf16 ? round_bf16(f) : f;
 }
 
+// 9 x 9 FP64 blocks -> packed BF16 blocks of the matrix-core tiles: row p holds
+// elements (p, m), m = 0..8, then 7 zeros (transpose: row p holds (m, p)).
+// Rounding as k_round_copy: to FP32, then to BF16, both to nearest even.
+__global__ void k_pack_bf16_blocks(int64_t nblk, const double *__restrict__ x, unsigned short *__restrict__ y,
+                                   int transpose)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nblk * kPackedBlock) return;
+    const int64_t blk = e / kPackedBlock;
+    const int w = (int)(e - blk * kPackedBlock), p = w >> 4, m = w & 15;
+    unsigned short v = 0;
+    if (m < 9) {
+        const double xv = x[blk * 81 + (transpose ? m * 9 + p : p * 9 + m)];
+        v = (unsigned short)(__float_as_uint(round_bf16((float)xv)) >> 16);
+    }
+    y[e] = v;
+}
+
+// BF16 matrix-core product tiles (b = 9, 4-row wave tiles), one per one-wave workgroup.
+__global__ __launch_bounds__(64) void k_product_mfma_bf16(
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const unsigned short *__restrict__ pA,
+    const unsigned short *__restrict__ pBt, const unsigned short *__restrict__ pz, double *__restrict__ vC,
+    double alpha, double beta)
+{
+    __shared__ __attribute__((aligned(16))) char ring[4 * 11 * kPackedBytes];
+    const int64_t t = logical_workgroup(nwg_padded);
+    if (t >= ntiles) return;
+    tile_mfma_bf16(order[t], hdr, ebeg, ent, pA, pBt, pz, vC, alpha, beta, (lds_char_t *)ring);
+}
+
 // ---------------------------------------------------------------- planner
 __device__ inline int find_in_row(const int *__restrict__ rp, const int *__restrict__ cols, int i, int j)
 {
@@ -534,6 +565,29 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     if (plan->G > 8) plan = get_plan_kind(ctx, PA, PB, PC, 0, default_rows_per_wave(PC->b));   // wave tiles
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
+    if (prec == BSM_BF16 && PC->b == 9 && plan->G == 4 && (plan->variant == 3 || plan->variant == 4)) {
+        // matrix cores: operands packed to BF16 (B transposed), FP32 accumulation
+        unsigned short *pa = reinterpret_cast<unsigned short *>(ctx->scratch_f32(0, PA->nnzb * (kPackedBlock / 2)));
+        unsigned short *pb = reinterpret_cast<unsigned short *>(ctx->scratch_f32(1, PB->nnzb * (kPackedBlock / 2)));
+        k_pack_bf16_blocks<<<(unsigned)((PA->nnzb * kPackedBlock + 255) / 256), 256, 0, st>>>(PA->nnzb, A, pa, 0);
+        k_pack_bf16_blocks<<<(unsigned)((PB->nnzb * kPackedBlock + 255) / 256), 256, 0, st>>>(PB->nnzb, Bm, pb, 1);
+        Context::ProfRec rec{plan, nullptr, nullptr, prec};
+        if (ctx->profiling) {
+            rec.start = ctx->take_event();
+            rec.stop = ctx->take_event();
+            BSM_HIP_TRY(hipEventRecord(rec.start, st));
+        }
+        const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
+        k_product_mfma_bf16<<<(unsigned)nwg_padded, 64, 0, st>>>(
+            plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+            plan->ent.as<int>(), pa, pb, ctx->zero_block.as<unsigned short>(), C, alpha, beta);
+        BSM_HIP_TRY(hipGetLastError());
+        if (ctx->profiling) {
+            BSM_HIP_TRY(hipEventRecord(rec.stop, st));
+            ctx->prof.push_back(rec);
+        }
+        return;
+    }
     const int64_t na = nelems(PA), nb = nelems(PB);
     float *a32 = ctx->scratch_f32(0, na), *b32 = ctx->scratch_f32(1, nb);
     const int bf = prec == BSM_BF16 ? 1 : 0;

@@ -665,4 +665,148 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
     }
 }
 
+// ---------------------------------------------------------------- BF16 matrix-core tiles (b = 9)
+// The same tiles (4 rows x 7 columns of 9 x 9 blocks) computed on the matrix
+// cores with v_mfma_f32_16x16x32_bf16.  Operands are pre-packed in BF16: every
+// A block as 9 rows of 16 (the contraction index m = 0..8 then 7 zeros),
+// every B block transposed the same way (row q holds B[m][q]), 288 bytes per
+// block, so each MFMA operand of a lane is one aligned 16-byte LDS read.  Two
+// consecutive entries form the K = 32 of one MFMA (16 per entry, 9 of them
+// live).  The tile's 36 output rows are 3 MFMA row tiles (48 rows, the last 12
+// padding), its 63 output columns 4 column tiles (64 columns).  Absent A or B
+// blocks are staged from a packed zero block.  Entries are copied into a
+// per-wave LDS ring of four slots by one 16-byte LDS-DMA per block (18 lanes),
+// one entry pair ahead of the multiply.  Products are exact in FP32 and summed
+// in FP32 in the matrix core's order.
+constexpr int kPackedBlock = 9 * 16;             // BF16 elements per packed block
+constexpr int kPackedBytes = kPackedBlock * 2;   // 288
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline void tile_mfma_bf16(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
+                                      const int *__restrict__ ent, const unsigned short *__restrict__ pA,
+                                      const unsigned short *__restrict__ pBt, const unsigned short *__restrict__ pz,
+                                      double *__restrict__ vC, double alpha, double beta, lds_char_t *ring)
+{
+    constexpr int B = 9, G = 4, JT = 7, BB = 81;
+    constexpr int HS = G + G * JT, ES = G + JT, NB = G + JT;
+    constexpr int SLOT = NB * kPackedBytes;          // bytes per ring slot (one entry)
+    constexpr int NI = NB;                           // DMA loads per entry
+    const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
+    const int e_of_lane = g >> 1, half = g & 1;      // which entry of the pair, which 16-byte half
+    const int *h = hdr + tile * HS;
+
+    const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
+    const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
+    const int n = (int)(e1 - e0);                    // even
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
+
+    // LDS byte offsets of this lane's operands inside a slot (-1: padding row / column)
+    int aoff[3], boff[4];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int r = 16 * t + l16;
+        aoff[t] = r < 36 ? (r / 9) * kPackedBytes + (r % 9) * 32 + half * 16 : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int cc = 16 * u + l16;
+        boff[u] = cc < 63 ? (G + cc / 9) * kPackedBytes + (cc % 9) * 32 + half * 16 : -1;
+    }
+    f32x4_t acc[3][4];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    // copy entry q into ring slot P (18 lanes x 16 bytes per block)
+    auto issue = [&](auto P, int q) {
+        lds_char_t *slot = ring + decltype(P)::value * SLOT;
+        int sl[NB];
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) sl[blk] = entu[(int64_t)q * ES + blk];
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) {
+            const unsigned short *src =
+                sl[blk] >= 0 ? (blk < G ? pA : pBt) + (int64_t)sl[blk] * kPackedBlock : pz;
+            if (lane < kPackedBytes / 16)
+                __builtin_amdgcn_global_load_lds((const void *)(reinterpret_cast<const char *>(src) + 16 * lane),
+                                                 (lds_void_t *)(slot + blk * kPackedBytes), 16, 0, 0);
+        }
+    };
+    auto wait_for = [&](int later) {   // entries issued after the pair being waited for
+        if (later >= 2) wait_vmcnt<2 * NI>();
+        else wait_vmcnt<0>();
+    };
+    auto zero8 = []() {
+        bf16x8_t z;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+        return z;
+    };
+    // the pair of entries in slots (P, P + 1)
+    auto compute = [&](auto P) {
+        const lds_char_t *slot = ring + (decltype(P)::value + e_of_lane) * SLOT;
+        bf16x8_t av[3], bv[4];
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+            av[t] = aoff[t] >= 0 ? *(const __attribute__((address_space(3))) bf16x8_t *)(slot + aoff[t]) : zero8();
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            bv[u] = boff[u] >= 0 ? *(const __attribute__((address_space(3))) bf16x8_t *)(slot + boff[u]) : zero8();
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], bv[u], acc[t][u], 0, 0, 0);
+    };
+
+    // ring of 4 slots: pair s in slots 2 (s % 2), 2 (s % 2) + 1; pair s + 1 loads meanwhile
+    if (0 < n) {
+        issue(std::integral_constant<int, 0>{}, 0);
+        issue(std::integral_constant<int, 1>{}, 1);
+    }
+    for (int q0 = 0; q0 < n; q0 += 4) {
+        auto step = [&](auto S) {   // S = 0: entries q0, q0 + 1 in slots 0, 1; S = 1: q0 + 2, q0 + 3 in 2, 3
+            constexpr int s = decltype(S)::value;
+            const int q = q0 + 2 * s;
+            if (q >= n) return;
+            const bool more = q + 2 < n;
+            if (more) {
+                issue(std::integral_constant<int, 2 * (1 - s)>{}, q + 2);
+                issue(std::integral_constant<int, 2 * (1 - s) + 1>{}, q + 3);
+            }
+            wait_for(more ? 2 : 0);
+            compute(std::integral_constant<int, 2 * s>{});
+        };
+        step(std::integral_constant<int, 0>{});
+        step(std::integral_constant<int, 1>{});
+    }
+
+    // epilogue: lane holds rows 16 t + 4 g + i of column 16 u + l16 of tile (t, u)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int cc = 16 * u + l16;
+        if (cc >= 63) continue;
+        const int jj = cc / 9, q = cc % 9;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * t + 4 * g + i;
+                if (r >= 36) continue;
+                const int a = r / 9, p = r % 9;
+                const int cs = h[G + a * JT + jj];
+                if (cs < 0) continue;
+                double *cp = vC + (int64_t)cs * BB + p * B + q;
+                const double v = alpha * (double)acc[t][u][i];
+                *cp = beta == 0.0 ? v : v + beta * *cp;
+            }
+        }
+    }
+}
+
 }  // namespace bsm

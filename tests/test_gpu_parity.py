@@ -404,13 +404,19 @@ def test_w_class_product_4096_sampled(bsm, ctx):
 
 
 # ------------------------------------------------------------------ mixed precision and diagnostics
-@pytest.mark.parametrize("prec", [1, 2])
-@pytest.mark.parametrize("b", [4, 9])
-def test_mixed_product_parity(bsm, ctx, prec, b):
-    """FP32 / BF16-rounded operands, FP32 accumulation: the oracle's result up to
-    the FP64 epilogue (same rounding, same accumulation order)."""
+@pytest.mark.parametrize("prec,b,variant", [(1, 4, -1), (1, 9, -1), (2, 4, -1), (2, 9, 1), (2, 9, -1)])
+def test_mixed_product_parity(bsm, prec, b, variant):
+    """FP32 / BF16-rounded operands, FP32 accumulation.  VALU kernels: the oracle's
+    result up to the FP64 epilogue (same rounding, same accumulation order).  BF16
+    with b = 9 on the matrix cores (the default): the same BF16 inputs and exact
+    FP32 products, summed in the matrix core's order, so the sums differ from the
+    oracle's FMA chain by FP32 rounding only: checked against the oracle at 2e-6 of
+    the result scale (a few hundred terms per element, FP32 unit roundoff 6e-8)."""
+    ctx = bsm.Context(0)
+    ctx.set_product_variant(variant)
+    mfma = prec == 2 and b == 9 and variant == -1
     s = SYSTEMS["si256_disp"]()
-    say(f"mixed product prec={prec} b={b}")
+    say(f"mixed product prec={prec} b={b} variant={variant}")
     gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
     op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
     for n, (ra, rb, rc) in enumerate([(6, 8, 14), (14, 8, 6)]):
@@ -421,7 +427,10 @@ def test_mixed_product_parity(bsm, ctx, prec, b):
         bsm.multiply_truncate_prec(prec, 0.5, A, B, 0.25, C)
         Co = O.Matrix(op[rc], b, c0.copy())
         O.multiply_truncate_mixed(prec, 0.5, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), 0.25, Co)
-        assert rel_err(host(C), Co.blocks) < 1e-14
+        err = rel_err(host(C), Co.blocks)
+        say(f"   P{ra} x P{rb} -> P{rc}: {err:.3e}")
+        assert err < (2e-6 if mfma else 1e-14)
+    ctx.close()
 
 
 @pytest.mark.parametrize("b", [4, 9])
