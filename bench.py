@@ -349,7 +349,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU domain "
-              "decomposition is a design note, not part of this build", file=sys.stderr)
+              "decomposition is designed but not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -198,13 +198,16 @@ int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const 
  * BSM_F32 (round to nearest even) or BSM_BF16 (to FP32, then to 8 significant
  * bits, nearest even); products accumulated in FP32 by fused multiply-adds over
  * k ascending, then the block's inner index ascending; the FP32 sum is widened
- * exactly to FP64 and C <- alpha sum + beta C in FP64.  BSM_F64 is
- * bsm_multiply_truncate.  A and B stay FP64 in memory; their rounded copies live
- * in context scratch.  Used for the low-precision stages of an LNV solve with
- * FP64 traces and refinement (spec extension, not in the paper). */
+ * exactly to FP64 and C <- alpha sum + beta C in FP64.  Exception: BSM_BF16 with
+ * b = 9 and the default kernel runs on the matrix cores (products exact in FP32,
+ * summed in FP32 in the matrix core's order), so its sums differ from the FMA
+ * chain by FP32 rounding.  BSM_F64 is bsm_multiply_truncate.  A and B stay FP64
+ * in memory; their rounded (or packed) copies live in context scratch.  Used for
+ * the low-precision stages of an LNV solve with FP64 traces and refinement (an
+ * extension built on the method, not in the paper). */
 int bsm_multiply_truncate_prec(bsm_ctx ctx, int precision, double alpha, const bsm_matrix *A,
                                const bsm_matrix *B, double beta, const bsm_matrix *C);
-/* ---- many products in one persistent launch (spec extension) --------
+/* ---- many products in one persistent launch (an extension: uneven systems) 
  * A batch of independent products C_p <- alpha_p mask(A_p B_p) + beta_p C_p,
  * b = 4 or 9 (e.g. one per system of a batch of uneven systems), runs as one
  * launch of resident wavefronts that take tiles from work queues until the list
@@ -338,7 +341,7 @@ int lnv_state_destroy(lnv_state *st);
  * (harmless: every step recomputes it).  Synchronises. */
 int lnv_idempotency_error(lnv_state *st, double *e_idem);
 
-/* A precision schedule for a whole solve (spec extension: low-precision
+/* A precision schedule for a whole solve (an extension built on the method: low-precision
  * products with FP64 traces, then FP64 refinement).  Stage s runs lnv_step with
  * products in precision[s] until |dE| < tol_E[s] (tol_E[s] > 0), or, when
  * stop_on_rise[s], until E fails to decrease (the rounding floor of that

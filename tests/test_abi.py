@@ -28,7 +28,7 @@ def test_header_declares_the_hot_path():
 
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(LIB):
-        pytest.fail("libbsm.so is not built (run __graft_entry__.build())")
+        pytest.fail("libbsm.so is not built (run python paper_2205_08941_amd/build.py)")
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
