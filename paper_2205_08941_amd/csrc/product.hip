@@ -281,6 +281,23 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restr
             for (int a = 0; a < G; ++a) ntri += (aslot[a] >= 0 && h[G + a * jt + x] >= 0) ? 1 : 0;
         }
         if (ntri == 0) continue;
+        // A row (B column) blocks with no live triple in this entry would only
+        // meet zero blocks or outputs outside P_C: drop them, so that the kernels
+        // neither copy nor multiply them
+        unsigned rowlive = 0;
+        unsigned long long collive = 0;
+        for (int x = 0; x < jt; ++x) {
+            if (bslot[x] < 0) continue;
+            for (int a = 0; a < G; ++a)
+                if (aslot[a] >= 0 && h[G + a * jt + x] >= 0) {
+                    rowlive |= 1u << a;
+                    collive |= 1ull << x;
+                }
+        }
+        for (int a = 0; a < G; ++a)
+            if (!((rowlive >> a) & 1u)) aslot[a] = -1;
+        for (int x = 0; x < jt; ++x)
+            if (!((collive >> x) & 1ull)) bslot[x] = -1;
         if (MODE == 1) {
             int *e = ent + w * es;
             for (int a = 0; a < G; ++a) e[a] = aslot[a];
