@@ -520,15 +520,21 @@ template <int VM> __device__ inline void wait_vmcnt()
     __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// Instruction I of a block's DMA copies dwords 64 I + lane (the last one only
-// for the lanes inside the block); the immediate offset 256 I moves both the
-// global and the LDS address.
+// Instruction I of a block's DMA copies dwords s_I + lane with s_I = 64 I,
+// except that the last instruction of a block longer than 64 dwords starts at
+// DW - 64: every lane copies (dwords below 64 I are copied twice, with the same
+// values), so no lane mask and no branch is needed.  A block shorter than 64
+// dwords is copied by the lanes below DW.  The immediate offset 4 s_I moves
+// both the global and the LDS address.
 template <int IPB, int DW, int... I>
 __device__ inline void dma_block(const char *g, lds_void_t *l, int lane, std::integer_sequence<int, I...>)
 {
-    ((I < IPB - 1 || 64 * I + lane < DW ? __builtin_amdgcn_global_load_lds((const void *)g, l, 4, 256 * I, 0)
-                                        : (void)0),
-     ...);
+    if constexpr (DW >= 64) {
+        (__builtin_amdgcn_global_load_lds((const void *)g, l, 4, 4 * (I < IPB - 1 ? 64 * I : DW - 64), 0), ...);
+    } else {
+        static_assert(IPB == 1, "one instruction per short block");
+        if (lane < DW) __builtin_amdgcn_global_load_lds((const void *)g, l, 4, 0, 0);
+    }
 }
 
 // T = double: FP64 product.  T = float: operands already rounded (FP32, or BF16
@@ -586,8 +592,10 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
         for (int a = 0; a < G; ++a) asl[a] = sl[a];
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) {
-            const T *src = sl[blk] >= 0 ? (blk < G ? vA : vB) + (int64_t)sl[blk] * BB : zblk;
-            const char *g = reinterpret_cast<const char *>(src) + lane4;
+            // absent blocks (slot -1) copy the zero block; selected with masks, not a branch
+            const uint64_t real = (uint64_t)(blk < G ? vA : vB) + (uint64_t)((int64_t)sl[blk] * (BB * ESZ));
+            const uint64_t neg = (uint64_t)(int64_t)(sl[blk] >> 31);
+            const char *g = reinterpret_cast<const char *>((real & ~neg) | ((uint64_t)zblk & neg)) + lane4;
             lds_void_t *l = (lds_void_t *)(slot + blk * (BB * ESZ));
             dma_block<IPB, DW>(g, l, lane, std::make_integer_sequence<int, IPB>{});
         }
