@@ -580,14 +580,19 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
     const int n = (int)(e1 - e0);
     const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
 
-    // Copy entry q (< n) into ring position P; keep its A slots in `asl`.  The
-    // DMA's immediate offset advances the global and the LDS address together.
+    // Copy an entry, given its slots, into ring position P; keep its A slots in
+    // `asl`.  The DMA's immediate offset advances the global and the LDS address
+    // together.  The slots of the entry copied next are loaded (scalar loads)
+    // before the current copies are issued, so their latency overlaps them; near
+    // the tile's end these loads read the next tile's entries or the plan's four
+    // spare entries, which are not used.
     const int lane4 = 4 * lane;
-    auto issue = [&](auto P, int q, int (&asl)[G]) {
-        lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
-        int sl[NB];
+    auto load_slots = [&](int q, int (&sl)[NB]) {
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) sl[blk] = entu[(int64_t)q * ES + blk];
+    };
+    auto issue = [&](auto P, const int (&sl)[NB], int (&asl)[G]) {
+        lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
 #pragma unroll
         for (int a = 0; a < G; ++a) asl[a] = sl[a];
 #pragma unroll
@@ -600,11 +605,10 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
             dma_block<IPB, DW>(g, l, lane, std::make_integer_sequence<int, IPB>{});
         }
     };
-    // wait until at most `later` entries' loads are outstanding
-    auto wait_for = [&](int later) {
-        if (later >= 2) wait_vmcnt<(2 * NI < 63 ? 2 * NI : 63)>();
-        else if (later == 1) wait_vmcnt<(NI < 63 ? NI : 63)>();
-        else wait_vmcnt<0>();
+    // at most `later` entries' copies still in flight
+    auto wait_for = [&](auto L) {
+        constexpr int later = decltype(L)::value;
+        wait_vmcnt<(later * NI < 63 ? later * NI : 63)>();
     };
     // multiply the entry held at ring position P
     auto compute = [&](auto P, const int (&as)[G]) {
@@ -630,35 +634,55 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
                 if (as[a] >= 0) read_row(xa[a], a);
             dpp_entry<B, G, NA, T>(as, xa, bv, acc);
         } else {
-            // row by row, so that only one row of A is live next to 8 rows of sums
+            // two rows of A live next to 8 rows of sums: row a + 1 is read while
+            // row a is multiplied (a row without A reads a block it does not use)
+            T xr[2][NA];
+            read_row(xr[0], 0);
 #pragma unroll
             for (int a = 0; a < G; ++a) {
-                if (as[a] < 0) continue;
-                T xr[NA];
-                read_row(xr, a);
-                fma_block<B, NA, T>(acc[a], xr, bv, std::make_integer_sequence<int, B>{});
+                if (a + 1 < G) read_row(xr[(a + 1) & 1], a + 1);
+                if (as[a] >= 0) fma_block<B, NA, T>(acc[a], xr[a & 1], bv, std::make_integer_sequence<int, B>{});
             }
         }
     };
     static_assert(D >= 2 && D <= 3, "ring depth 2 or 3");
 
+    // Every step copies the entry D - 1 ahead, also past the tile's end (the
+    // next tile's entries or the plan's spare entries: in bounds, never
+    // multiplied), so the steps are straight-line code and each waits for the
+    // same count; the tile ends by draining its copies.  sbuf[p] holds the slots
+    // of the entry copied next into ring position p; they are loaded one step
+    // ahead, up to D entries past the tile.  Entry counts are even, so for D = 2
+    // both steps of an iteration are inside the tile.
     int asl[D][G];
-    if (0 < n) issue(std::integral_constant<int, 0>{}, 0, asl[0]);
-    if (D == 3 && 1 < n) issue(std::integral_constant<int, 1 % D>{}, 1, asl[1 % D]);
+    int sbuf[D][NB];
+    if (n > 0) {
+        load_slots(0, sbuf[0]);
+        load_slots(1, sbuf[1]);
+        issue(std::integral_constant<int, 0>{}, sbuf[0], asl[0]);
+        if constexpr (D == 3) {
+            load_slots(2, sbuf[2]);
+            issue(std::integral_constant<int, 1>{}, sbuf[1], asl[1]);
+        }
+    }
     for (int q0 = 0; q0 < n; q0 += D) {
         // ring position of entry q0 + r is r; entry q0 + r + D - 1 goes to (r + D - 1) % D
         auto step = [&](auto R) {
             constexpr int r = decltype(R)::value;
-            const int q = q0 + r;
-            if (q >= n) return;
-            if (q + D - 1 < n) issue(std::integral_constant<int, (r + D - 1) % D>{}, q + D - 1, asl[(r + D - 1) % D]);
-            wait_for(min(D - 1, n - 1 - q));
+            constexpr int pn = (r + D - 1) % D;
+            if constexpr (D == 3)
+                if (q0 + r >= n) return;
+            load_slots(q0 + r + D, sbuf[r]);   // entry q0 + r's slots are no longer needed
+            __builtin_amdgcn_sched_barrier(0);    // these loads first: their latency overlaps the copies
+            issue(std::integral_constant<int, pn>{}, sbuf[pn], asl[pn]);
+            wait_for(std::integral_constant<int, D - 1>{});
             compute(std::integral_constant<int, r>{}, asl[r]);
         };
         step(std::integral_constant<int, 0>{});
         step(std::integral_constant<int, 1>{});
         if constexpr (D == 3) step(std::integral_constant<int, 2>{});
     }
+    wait_vmcnt<0>();
 #pragma unroll
     for (int a = 0; a < G; ++a) {
         if (!cact[a]) continue;
