@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=-1,
                     help="product kernel variant for --mode product (-1: the library default)")
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"],
+                    help="operand precision of the --mode product launches")
     ap.add_argument("--rows", type=int, default=0,
                     help="rows per tile for --mode product (0: the library default)")
     ap.add_argument("--mode", default="solve", choices=["solve", "product"],
@@ -82,9 +84,10 @@ def product_mode(args):
     X = bsm.Matrix(P, torch.rand((P.nnzb, b, b), dtype=torch.float64, device=ctx.device, generator=g) - 0.5)
     C = bsm.Matrix(P)
     flops = bsm.product_flops(P, P, P)
+    prec = {"f64": bsm.F64, "f32": bsm.F32, "bf16": bsm.BF16}[args.prec]
     ctx.set_profiling(True)
     for k in range(args.steps):
-        bsm.multiply_truncate(1.0, X, X, 0.0, C)
+        bsm.multiply_truncate_prec(prec, 1.0, X, X, 0.0, C)
         torch.cuda.synchronize()
         log(f"[product] launch {k}")
     st = ctx.product_stats()[0]
@@ -94,7 +97,8 @@ def product_mode(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     ms = st["ms"] / st["launches"]
-    print(json.dumps({"mode": "product", "kernel": kernel_name(st), "sources_sha256_16": kernel_sources_sha(),
+    print(json.dumps({"mode": "product", "precision": args.prec, "kernel": kernel_name(st),
+                      "sources_sha256_16": kernel_sources_sha(),
                       "flops_per_launch": flops, "avg_ms": ms,
                       "tflops": flops / (ms * 1e-3) / 1e12, "blocks": P.nnzb,
                       "algorithmic_bytes": 3 * P.nnzb * b * b * 8, "copy_bytes": 2 * src.numel() * 8}),
@@ -327,9 +331,12 @@ def kernel_sources_sha() -> str:
 
 
 def kernel_name(st) -> str:
-    b, g, v = st["b"], st["rows"], st["variant"]
-    return {0: f"k_product_sgpr<{b}, {g}>", 1: f"k_product_f64_dpp<{b}, {g}>", 2: f"k_product_wg<{b}>",
+    b, g, v, p = st["b"], st["rows"], st["variant"], st.get("precision", 0)
+    if p == 2 and b == 9 and g == 4 and v in (3, 4):
+        return "k_product_mfma_bf16<9, 4>"
+    name = {0: f"k_product_sgpr<{b}, {g}>", 1: f"k_product_f64_dpp<{b}, {g}>", 2: f"k_product_wg<{b}>",
             3: f"k_product_ring<{b}, {g}, 3>", 4: f"k_product_ring<{b}, {g}, 2>"}.get(v, f"variant {v}")
+    return name if p == 0 else name + (" (FP32)" if p == 1 else " (BF16-rounded, FP32)")
 
 
 def measured_traffic(name: str):

@@ -119,7 +119,8 @@ typedef struct {
 } bsm_product_stat;
 
 /* Rows of C per wavefront tile in product plans built from now on: 2, 4 or 8
- * (0 restores the default for the orbital count); variant 2 plans always use
+ * (0 restores the default: 8 for the default kernel with b = 4 and 9, else 4
+ * for b >= 4 and 2 below); variant 2 plans always use
  * 16-row workgroup tiles.  Larger values reuse each B block across more rows at
  * the cost of idle lanes.  Clears cached plans (destroy batches first). */
 int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
@@ -130,8 +131,8 @@ int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
  * LDS, A as in 1; b = 4 and 9, else 0); 3 and 4 = the wave tiles of 1 with
  * both operands copied into a per-wave LDS ring by asynchronous LDS-DMA loads,
  * 2 (3) or 1 (4) entries ahead (b = 4 and 9, rows 2, 4 or 8, else 0); -1 =
- * default (4 for b = 4 and 9, with 8 rows per tile for b = 4, else 0).  Variants 1 and 2 multiply absent (k, j) blocks by zero instead of
- * skipping them, so a non-finite block of A can make other blocks of its
+ * default (4 for b = 4 and 9, with 8 rows per tile, else 0).  Variants 1 to 4
+ * multiply absent (k, j) blocks by zero instead of skipping them, so a non-finite block of A can make other blocks of its
  * output row non-finite.  Clears cached plans (a bsm_batch made before keeps
  * pointers to them: destroy batches first). */
 int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant);
@@ -199,8 +200,9 @@ int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const 
  * bits, nearest even); products accumulated in FP32 by fused multiply-adds over
  * k ascending, then the block's inner index ascending; the FP32 sum is widened
  * exactly to FP64 and C <- alpha sum + beta C in FP64.  Exception: BSM_BF16 with
- * b = 9 and the default kernel runs on the matrix cores (products exact in FP32,
- * summed in FP32 in the matrix core's order), so its sums differ from the FMA
+ * b = 9, kernel variant 3 or 4 and the default rows per tile runs on the matrix
+ * cores, over 4-row tiles (products exact in FP32, summed in FP32 in the matrix
+ * core's order), so its sums differ from the FMA
  * chain by FP32 rounding.  BSM_F64 is bsm_multiply_truncate.  A and B stay FP64
  * in memory; their rounded (or packed) copies live in context scratch.  Used for
  * the low-precision stages of an LNV solve with FP64 traces and refinement (an

@@ -582,6 +582,10 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     if (plan->G > 8) plan = get_plan_kind(ctx, PA, PB, PC, 0, default_rows_per_wave(PC->b));   // wave tiles
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
+    // BF16, b = 9: matrix cores over 4-row tiles (the default rows per tile of the ring is 8)
+    if (prec == BSM_BF16 && PC->b == 9 && plan->G == 8 && ctx->rows_per_wave == 0 &&
+        (plan->variant == 3 || plan->variant == 4))
+        plan = get_plan_kind(ctx, PA, PB, PC, plan->variant, 4);
     if (prec == BSM_BF16 && PC->b == 9 && plan->G == 4 && (plan->variant == 3 || plan->variant == 4)) {
         // matrix cores: operands packed to BF16 (B transposed), FP32 accumulation
         unsigned short *pa = reinterpret_cast<unsigned short *>(ctx->scratch_f32(0, PA->nnzb * (kPackedBlock / 2)));
@@ -657,7 +661,7 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
     int variant = ctx->product_variant >= 0 ? ctx->product_variant : default_variant(C->b);
     if (variant >= 2 && C->b != 9 && C->b != 4) variant = 0;
     int G = variant == 2 ? kMaxRows : (ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b));
-    if (variant == 4 && C->b == 4 && ctx->rows_per_wave == 0) G = 8;   // measured best for the b = 4 ring
+    if (variant == 4 && (C->b == 4 || C->b == 9) && ctx->rows_per_wave == 0) G = 8;   // measured best for the ring
     return get_plan_kind(ctx, A, B, C, variant, G);
 }
 
