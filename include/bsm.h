@@ -213,8 +213,11 @@ int bsm_multiply_truncate_prec(bsm_ctx ctx, int precision, double alpha, const b
  * A batch of independent products C_p <- alpha_p mask(A_p B_p) + beta_p C_p,
  * b = 4 or 9 (e.g. one per system of a batch of uneven systems), runs as one
  * launch of resident wavefronts that take tiles from work queues until the list
- * is exhausted.  Results equal the separate products bit for bit (tiles write
- * disjoint outputs).  The schedule (bsm_batch_config) is chosen by
+ * is exhausted.  Tiles are the 8-row LDS-ring tiles of the separate launches;
+ * results equal the separate products bit for bit (tiles write disjoint
+ * outputs), except BF16 with b = 9, which the batch multiplies on the VALU (FP32
+ * fused multiply-adds, as the separate product with explicit rows per tile)
+ * while the default separate product uses the matrix cores.  The schedule (bsm_batch_config) is chosen by
  * bsm_batch_tune, which times every candidate on the batch itself. */
 typedef struct bsm_batch_s *bsm_batch;
 enum { BSM_ORDER_BY_PRODUCT = 0, BSM_ORDER_HEAVY_FIRST = 1, BSM_ORDER_INTERLEAVE = 2 };
@@ -226,8 +229,8 @@ typedef struct {
 /* n products; A, B, C arrays of n matrices (C_p must not overlap A_p or B_p),
  * alpha, beta arrays of n.  precision: BSM_F64, BSM_F32 or BSM_BF16 (as in
  * bsm_multiply_truncate_prec).  Builds (or reuses) each product's plan.  The
- * matrices must outlive the batch.  Errors: BSM_EINVAL (b not 4 or 9, plan not
- * at 4 rows per wave), BSM_EPATTERN, BSM_ENOMEM. */
+ * matrices must outlive the batch.  Errors: BSM_EINVAL (b not 4 or 9),
+ * BSM_EPATTERN, BSM_ENOMEM. */
 int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *B, const bsm_matrix *C,
                      const double *alpha, const double *beta, int precision, bsm_batch *out);
 /* Queue the batch on the context stream; cfg NULL = the tuned (or default) schedule. */

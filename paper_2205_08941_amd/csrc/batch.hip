@@ -29,8 +29,9 @@
 namespace bsm {
 
 // product kinds handled by the persistent kernel
-enum { kKindF64Ring9 = 0, kKindF64Dpp4 = 1, kKindF32Ring9 = 2, kKindF32b4 = 3 };
-constexpr int kBatchRing = 2;   // LDS ring depth of the b = 9 tiles
+enum { kKindF64Ring9 = 0, kKindF64Ring4 = 1, kKindF32Ring9 = 2, kKindF32Ring4 = 3 };
+constexpr int kBatchRing = 2;   // LDS ring depth of the tiles
+constexpr int kBatchRows = 8;   // rows per tile (the separate launches' default for b = 4 and 9)
 
 struct BatchDesc {
     int kind;
@@ -61,7 +62,10 @@ __global__ __launch_bounds__(64) void k_product_batch(const BatchDesc *__restric
                                                       unsigned *__restrict__ counters, const double *__restrict__ zblk)
 {
     using T = typename std::conditional<F64, double, float>::type;
-    __shared__ __attribute__((aligned(16))) char ring[kBatchRing * RingEntry<9, 4, T>::kBytes];
+    constexpr int kEntryBytes = RingEntry<9, kBatchRows, T>::kBytes > RingEntry<4, kBatchRows, T>::kBytes
+                                    ? RingEntry<9, kBatchRows, T>::kBytes
+                                    : RingEntry<4, kBatchRows, T>::kBytes;
+    __shared__ __attribute__((aligned(16))) char ring[kBatchRing * kEntryBytes];
     const int lane = threadIdx.x & 63;
     const int q = (int)(blockIdx.x % (unsigned)nq);   // workgroups are dealt round-robin to the XCDs
     const int64_t base = qbeg[q];
@@ -77,20 +81,22 @@ __global__ __launch_bounds__(64) void k_product_batch(const BatchDesc *__restric
         const int kind = __builtin_amdgcn_readfirstlane(d.kind);
         if constexpr (F64) {
             if (kind == kKindF64Ring9)
-                tile_ring<9, 4, kBatchRing, double>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A,
-                                                    (const double *)d.B, zblk, d.C, d.alpha, d.beta,
-                                                    (lds_char_t *)ring);
+                tile_ring<9, kBatchRows, kBatchRing, double>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A,
+                                                             (const double *)d.B, zblk, d.C, d.alpha, d.beta,
+                                                             (lds_char_t *)ring);
             else
-                tile_dpp<4, 4>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A, (const double *)d.B, zblk, d.C,
-                               d.alpha, d.beta);
+                tile_ring<4, kBatchRows, kBatchRing, double>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A,
+                                                             (const double *)d.B, zblk, d.C, d.alpha, d.beta,
+                                                             (lds_char_t *)ring);
         } else {
             if (kind == kKindF32Ring9)
-                tile_ring<9, 4, kBatchRing, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A,
-                                                   (const float *)d.B, (const float *)zblk, d.C, d.alpha, d.beta,
-                                                   (lds_char_t *)ring);
+                tile_ring<9, kBatchRows, kBatchRing, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A,
+                                                            (const float *)d.B, (const float *)zblk, d.C, d.alpha,
+                                                            d.beta, (lds_char_t *)ring);
             else
-                tile_sgpr<4, 4, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A, (const float *)d.B, d.C,
-                                       d.alpha, d.beta);
+                tile_ring<4, kBatchRows, kBatchRing, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A,
+                                                            (const float *)d.B, (const float *)zblk, d.C, d.alpha,
+                                                            d.beta, (lds_char_t *)ring);
         }
     }
 }
@@ -255,8 +261,8 @@ int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *
         check_same_shape(&A[p], &C[p]);
         const int b = C[p].pattern->b;
         BSM_REQUIRE(b == 4 || b == 9, BSM_EINVAL, "batched products support b = 4 and 9");
-        // wave tiles of 4 rows (the plans the separate launches use by default)
-        Plan *plan = get_plan_kind(c, A[p].pattern, B[p].pattern, C[p].pattern, b == 9 ? 4 : 1, 4);
+        // LDS-ring tiles of 8 rows (the plans the separate launches use by default)
+        Plan *plan = get_plan_kind(c, A[p].pattern, B[p].pattern, C[p].pattern, 4, kBatchRows);
         bt->plans.push_back(plan);
         bt->pa.push_back(A[p].pattern);
         bt->pb.push_back(B[p].pattern);
@@ -282,11 +288,11 @@ int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *
         x.alpha = alpha[p];
         x.beta = beta[p];
         if (precision == BSM_F64) {
-            x.kind = b == 9 ? kKindF64Ring9 : kKindF64Dpp4;
+            x.kind = b == 9 ? kKindF64Ring9 : kKindF64Ring4;
             x.A = A[p].blocks;
             x.B = B[p].blocks;
         } else {
-            x.kind = b == 9 ? kKindF32Ring9 : kKindF32b4;
+            x.kind = b == 9 ? kKindF32Ring9 : kKindF32Ring4;
             bt->a32.emplace_back(c, sizeof(float) * (size_t)std::max<int64_t>(1, bt->a_n.back()));
             bt->b32.emplace_back(c, sizeof(float) * (size_t)std::max<int64_t>(1, bt->b_n.back()));
             x.A = bt->a32.back().ptr;
