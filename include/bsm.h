@@ -130,11 +130,14 @@ int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
  * of 16 rows (4 wavefronts of 4 rows sharing the tile's B blocks, staged in
  * LDS, A as in 1; b = 4 and 9, else 0); 3 and 4 = the wave tiles of 1 with
  * both operands copied into a per-wave LDS ring by asynchronous LDS-DMA loads,
- * 2 (3) or 1 (4) entries ahead (b = 4 and 9, rows 2, 4 or 8, else 0); -1 =
- * default (4 for b = 4 and 9, with 8 rows per tile, else 0).  Variants 1 to 4
- * multiply absent (k, j) blocks by zero instead of skipping them, so a non-finite block of A can make other blocks of its
- * output row non-finite.  Clears cached plans (a bsm_batch made before keeps
- * pointers to them: destroy batches first). */
+ * 2 (3, at 2 or 4 rows) or 1 (4, and 3 at 8 rows) entries ahead (b = 4 and 9,
+ * rows 2, 4 or 8, else 0); 3 addresses the copies with 64-bit pointers, 4
+ * through buffer resources when A and B each hold at most 0xfffff000 bytes
+ * (else as 3); -1 = default (4 for b = 4 and 9, with 8 rows per tile, else 0).
+ * Variants 1 to 4 multiply absent (k, j) blocks by zero instead of skipping
+ * them, so a non-finite block of A can make other blocks of its output row
+ * non-finite.  Clears cached plans (a bsm_batch made before keeps pointers to
+ * them: destroy batches first). */
 int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant);
 /* Launch order of product tiles in plans built from now on: tiles of `span`
  * consecutive row groups are interleaved by column position (1 = group by

@@ -83,17 +83,20 @@ __global__ __launch_bounds__(256) void k_product_wg(
     tile_wg<B>(order[t], hdr, ebeg, ent, vA, vB, vC, alpha, beta, lds);
 }
 
-// One wave tile per one-wave workgroup, operands through a per-wave LDS ring.
-template <int B, int G, int D, class T = double>
+// One wave tile per one-wave workgroup, operands through a per-wave LDS ring
+// (BUF: copied through buffer resources of a_bytes and b_bytes).
+template <int B, int G, int D, class T = double, bool BUF = false>
 __global__ __launch_bounds__(64) void k_product_ring(
     int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
     const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const T *__restrict__ vA,
-    const T *__restrict__ vB, const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta)
+    const T *__restrict__ vB, const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta,
+    unsigned a_bytes, unsigned b_bytes)
 {
     __shared__ __attribute__((aligned(16))) char ring[D * RingEntry<B, G, T>::kBytes];
     const int64_t t = logical_workgroup(nwg_padded);
     if (t >= ntiles) return;
-    tile_ring<B, G, D, T>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta, (lds_char_t *)ring);
+    tile_ring<B, G, D, T, BUF>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta, (lds_char_t *)ring,
+                               a_bytes, b_bytes);
 }
 
 // ---------------------------------------------------------------- operand rounding
@@ -385,27 +388,34 @@ void launch_wg(hipStream_t st, const Plan *plan, const double *A, const double *
 
 template <int B, int G, int D, class T = double>
 void launch_ring(hipStream_t st, const Plan *plan, const T *A, const T *Bm, double *C, double alpha, double beta,
-                 const T *zblk)
+                 const T *zblk, int64_t a_bytes, int64_t b_bytes)
 {
     const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
-    k_product_ring<B, G, D, T><<<(unsigned)nwg_padded, 64, 0, st>>>(
-        plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
-        plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta);
+    // variant 4: buffer copies when both operands fit a buffer resource; variant 3: 64-bit addresses
+    const bool buf = plan->variant == 4 && a_bytes <= (int64_t)kBufMaxBytes && b_bytes <= (int64_t)kBufMaxBytes;
+    if (buf)
+        k_product_ring<B, G, D, T, true><<<(unsigned)nwg_padded, 64, 0, st>>>(
+            plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+            plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta, (unsigned)a_bytes, (unsigned)b_bytes);
+    else
+        k_product_ring<B, G, D, T, false><<<(unsigned)nwg_padded, 64, 0, st>>>(
+            plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+            plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta, 0u, 0u);
 }
 
 template <int B>
 void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
-              double beta, const double *zblk)
+              double beta, const double *zblk, int64_t a_bytes, int64_t b_bytes)
 {
     if constexpr (B == 9 || B == 4) {
         if (plan->variant == 3 || plan->variant == 4) {   // LDS ring, depth 3 or 2
             const bool deep = plan->variant == 3;
             switch (plan->G) {
-                case 2: deep ? launch_ring<B, 2, 3>(st, plan, A, Bm, C, alpha, beta, zblk)
-                             : launch_ring<B, 2, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
-                case 4: deep ? launch_ring<B, 4, 3>(st, plan, A, Bm, C, alpha, beta, zblk)
-                             : launch_ring<B, 4, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
-                case 8: launch_ring<B, 8, 2>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                case 2: deep ? launch_ring<B, 2, 3>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes)
+                             : launch_ring<B, 2, 2>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                case 4: deep ? launch_ring<B, 4, 3>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes)
+                             : launch_ring<B, 4, 2>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                case 8: launch_ring<B, 8, 2>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
                 default: break;
             }
         }
@@ -431,14 +441,14 @@ void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *B
 
 template <int B>
 void launch_b32(hipStream_t st, const Plan *plan, const float *A, const float *Bm, double *C, double alpha,
-                double beta, const float *zblk)
+                double beta, const float *zblk, int64_t a_bytes, int64_t b_bytes)
 {
     if constexpr (B == 9 || B == 4) {
         if (plan->variant == 3 || plan->variant == 4) {   // LDS ring, FP32 operands
             switch (plan->G) {
-                case 2: launch_ring<B, 2, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk); return;
-                case 4: launch_ring<B, 4, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk); return;
-                case 8: launch_ring<B, 8, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk); return;
+                case 2: launch_ring<B, 2, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                case 4: launch_ring<B, 4, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                case 8: launch_ring<B, 8, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
                 default: break;
             }
         }
@@ -546,8 +556,6 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
                         const double *A, const bsm_pattern_s *PB, const double *Bm, double beta,
                         const bsm_pattern_s *PC, double *C)
 {
-    (void)PA;
-    (void)PB;
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
     Context::ProfRec rec{plan, nullptr, nullptr, BSM_F64};
@@ -558,7 +566,7 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
     }
     switch (PC->b) {
 #define X(b) \
-    case b: launch_b<b>(st, plan, A, Bm, C, alpha, beta, ctx->zero_block.as<double>()); break;
+    case b: launch_b<b>(st, plan, A, Bm, C, alpha, beta, ctx->zero_block.as<double>(), 8 * nelems(PA), 8 * nelems(PB)); break;
         BSM_FOR_EACH_B(X)
 #undef X
         default: throw Error{BSM_EINVAL, "b must be in 1..16"};
@@ -622,7 +630,7 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     }
     switch (PC->b) {
 #define X(b) \
-    case b: launch_b32<b>(st, plan, a32, b32, C, alpha, beta, ctx->zero_block.as<float>()); break;
+    case b: launch_b32<b>(st, plan, a32, b32, C, alpha, beta, ctx->zero_block.as<float>(), 4 * na, 4 * nb); break;
         BSM_FOR_EACH_B(X)
 #undef X
         default: throw Error{BSM_EINVAL, "b must be in 1..16"};

@@ -537,14 +537,38 @@ __device__ inline void dma_block(const char *g, lds_void_t *l, int lane, std::in
     }
 }
 
+// The same copy through a raw buffer resource: voffset = the block's byte
+// offset + 4 lane.  An absent block (slot -1) has offset 2^32 - block bytes:
+// with the lane and immediate offsets it stays below 2^32 and above the
+// resource's size, so the range check returns zeros for every lane (no zero
+// block, no select).
+template <int IPB, int DW, int... I>
+__device__ inline void dma_block_buf(__amdgpu_buffer_rsrc_t rs, unsigned vo, lds_void_t *l, int lane,
+                                     std::integer_sequence<int, I...>)
+{
+    if constexpr (DW >= 64) {
+        (__builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 4, vo, 0, 4 * (I < IPB - 1 ? 64 * I : DW - 64), 0), ...);
+    } else {
+        static_assert(IPB == 1, "one instruction per short block");
+        if (lane < DW) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, l, 4, vo, 0, 0, 0);
+    }
+}
+
+// Largest operand (bytes) the buffer copies address: absent-block offsets
+// (2^32 - block bytes and up) must lie past it.
+constexpr unsigned kBufMaxBytes = 0xfffff000u;
+
 // T = double: FP64 product.  T = float: operands already rounded (FP32, or BF16
 // stored as FP32), FP32 fused multiply-adds in the same (k, m) order, the sums
 // widened to FP64 for alpha, beta and the store.
-template <int B, int G, int D, class T = double>
+// BUF: copies through raw buffer resources over A and B (a_bytes, b_bytes, each
+// at most kBufMaxBytes): one scalar multiply and one vector add per block
+// instead of 64-bit address arithmetic and a zero-block select.
+template <int B, int G, int D, class T = double, bool BUF = false>
 __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
                                  const int *__restrict__ ent, const T *__restrict__ vA, const T *__restrict__ vB,
                                  const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta,
-                                 lds_char_t *ring)
+                                 lds_char_t *ring, unsigned a_bytes = 0, unsigned b_bytes = 0)
 {
     using RE = RingEntry<B, G, T>;
     constexpr int ESZ = (int)sizeof(T);
@@ -591,18 +615,25 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) sl[blk] = entu[(int64_t)q * ES + blk];
     };
+    const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc((void *)vA, 0, (int)a_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc((void *)vB, 0, (int)b_bytes, 0x00020000);
     auto issue = [&](auto P, const int (&sl)[NB], int (&asl)[G]) {
         lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
 #pragma unroll
         for (int a = 0; a < G; ++a) asl[a] = sl[a];
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) {
-            // absent blocks (slot -1) copy the zero block; selected with masks, not a branch
-            const uint64_t real = (uint64_t)(blk < G ? vA : vB) + (uint64_t)((int64_t)sl[blk] * (BB * ESZ));
-            const uint64_t neg = (uint64_t)(int64_t)(sl[blk] >> 31);
-            const char *g = reinterpret_cast<const char *>((real & ~neg) | ((uint64_t)zblk & neg)) + lane4;
             lds_void_t *l = (lds_void_t *)(slot + blk * (BB * ESZ));
-            dma_block<IPB, DW>(g, l, lane, std::make_integer_sequence<int, IPB>{});
+            if constexpr (BUF) {
+                const unsigned vo = (unsigned)sl[blk] * (unsigned)(BB * ESZ) + (unsigned)lane4;
+                dma_block_buf<IPB, DW>(blk < G ? rsA : rsB, vo, l, lane, std::make_integer_sequence<int, IPB>{});
+            } else {
+                // absent blocks (slot -1) copy the zero block; selected with masks, not a branch
+                const uint64_t real = (uint64_t)(blk < G ? vA : vB) + (uint64_t)((int64_t)sl[blk] * (BB * ESZ));
+                const uint64_t neg = (uint64_t)(int64_t)(sl[blk] >> 31);
+                const char *g = reinterpret_cast<const char *>((real & ~neg) | ((uint64_t)zblk & neg)) + lane4;
+                dma_block<IPB, DW>(g, l, lane, std::make_integer_sequence<int, IPB>{});
+            }
         }
     };
     // at most `later` entries' copies still in flight
