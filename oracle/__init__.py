@@ -13,6 +13,9 @@ What it computes, and where it comes from:
 * Hotelling's iteration Z <- 2Z - Z S Z for the overlap inverse -- the paper's
   "linear scaling inversion of the overlap matrix" (Development Priorities),
   by the textbook iteration of Hotelling (1943) / Schulz (1933);
+* the inverse square root S^-1/2 (and S^1/2) by the coupled Newton-Schulz
+  iteration (Higham 1997), the companion of that inversion listed as the next
+  step after the hot path;
 * LNV density-matrix minimisation, K = 3LSL - 2LSLSL -- the paper's linear
   scaling O(N) ground-state solver (Background; Meeting the Exascale
   Challenges), in the non-orthogonal form of Li, Nunes and Vanderbilt (1993)
@@ -379,6 +382,75 @@ def hotelling_inverse(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: f
         it += 1
         hist.append(r)
     return HotellingResult(Z, status, it, hist, alpha)
+
+
+# ---------------------------------------------------------------------------
+# Inverse square root of the overlap matrix (coupled Newton-Schulz)
+# ---------------------------------------------------------------------------
+@dataclass
+class InvSqrtResult:
+    Z: Matrix              # S^-1/2 on the Z pattern
+    Y: Matrix              # S^1/2 on the same pattern
+    status: int
+    iterations: int
+    residuals: List[float]
+    alpha: float           # 1 / rho, rho the Gershgorin bound of S
+
+
+def inverse_sqrt(S: Matrix, z_pattern: Pattern, max_iter: int = 100, tol: float = 1e-12) -> InvSqrtResult:
+    """Truncated coupled Newton-Schulz iteration for S^-1/2 and S^1/2.
+
+    The paper names linear-scaling inversion of the overlap matrix as key
+    (Development Priorities); this is the inverse-square-root companion of the
+    Hotelling iteration, in the coupled form analysed by Higham (1997,
+    "Stable iterations for the matrix square root"): with A = S / rho (rho the
+    Gershgorin bound, so the spectrum of A lies in (0, 1] for SPD S),
+    Y0 = mask_Z(A), Z0 = I and, per update,
+        P = Z Y,  T = (3 I - P) / 2,  Y <- Y T,  Z <- T Z,
+    so that Y -> A^1/2 and Z -> A^-1/2.  Truncation as for Hotelling: only the
+    iterates Y and Z are truncated (to the Z pattern, then symmetrised
+    blockwise); P and T are held exactly on P(2 r_Z).  The residual
+    ||I - Z Y||_F is summed elementwise over P - I.  The stop rules are
+    Hotelling's (tolerance, max_iter, no real progress: accepted at or below
+    0.1 sqrt(N_b), else divergence).  Returned: Z / sqrt(rho) = S^-1/2 and
+    sqrt(rho) Y = S^1/2.
+    """
+    nb, b = S.nrows, S.b
+    P2 = derived_pattern(z_pattern, 2.0 * z_pattern.cutoff)
+    rho = gershgorin_bound(S)
+    alpha = 1.0 / rho
+    Y = mask_copy(S, z_pattern)
+    Y = Matrix(z_pattern, b, alpha * Y.blocks)
+    Z = identity(z_pattern, b)
+    P = product(Z, Y, P2)
+    r = _hotelling_residual(P, nb)
+    hist, it, status = [r], 0, OK
+    if not math.isfinite(r):
+        status = ENONFINITE
+    while status == OK:
+        if tol > 0 and r < tol * math.sqrt(nb):
+            break
+        if it == max_iter:
+            status = ENOTCONV if tol > 0 else OK
+            break
+        T = Matrix(P2, b, -0.5 * P.blocks)
+        T.blocks[P2.diag_slots()] += 1.5 * np.eye(b)
+        Ynew = symmetrize(product(Y, T, z_pattern))
+        Znew = symmetrize(product(T, Z, z_pattern))
+        Pnew = product(Znew, Ynew, P2)
+        rnew = _hotelling_residual(Pnew, nb)
+        if not math.isfinite(rnew):
+            status = ENONFINITE
+            break
+        if rnew >= HOTELLING_PROGRESS * r:   # no real progress: the floor (accept) or divergence
+            status = OK if r <= 0.1 * math.sqrt(nb) else EDIVERGED
+            break
+        Y, Z, P, r = Ynew, Znew, Pnew, rnew
+        it += 1
+        hist.append(r)
+    zs, ys = 1.0 / math.sqrt(rho), math.sqrt(rho)
+    return InvSqrtResult(Matrix(z_pattern, b, zs * Z.blocks), Matrix(z_pattern, b, ys * Y.blocks),
+                         status, it, hist, alpha)
 
 
 # ---------------------------------------------------------------------------
