@@ -292,6 +292,23 @@ typedef struct {
 int hotelling_inverse(bsm_ctx ctx, const bsm_matrix *S, const bsm_matrix *Z,
                       const hot_params *params, hot_result *result);
 
+/* Inverse square root of the overlap matrix (the companion of its inversion,
+ * Development Priorities, for symmetric orthogonalisation): the coupled
+ * Newton-Schulz iteration (Higham 1997) on A = S / rho, rho the largest
+ * absolute row sum of S: Y0 = mask_Z(A), Z0 = I, then per update
+ * P = Z Y, T = (3 I - P) / 2, Y <- sym(mask_Z(Y T)), Z <- sym(mask_Z(T Z)),
+ * with P and T held exactly on P(2 r_Z) and the residual ||I - Z Y||_F summed
+ * elementwise over P - I.  Stops as hotelling_inverse (tolerance, max_iter, no
+ * real progress: accepted at or below 0.1 sqrt(N_b), else BSM_EDIVERGED).
+ * On return Z holds S^-1/2 = Z_k / sqrt(rho) and, when Y is not NULL,
+ * Y holds S^1/2 = sqrt(rho) Y_k, both on Z's pattern (Y must be built on the
+ * same pattern object).  params->init_given must be 0; result->alpha = 1 / rho.
+ * S, Z and Y must not alias.  Returns as hotelling_inverse (BSM_ENOTCONV is
+ * returned as BSM_OK with the outputs valid); BSM_EPATTERN if Y is on another
+ * pattern. */
+int bsm_inverse_sqrt(bsm_ctx ctx, const bsm_matrix *S, const bsm_matrix *Z, const bsm_matrix *Y,
+                     const hot_params *params, hot_result *result);
+
 /* ---- LNV density-matrix minimisation (paper: the linear-scaling O(N)
  *      solver, Background; its full GPU form, Meeting the Exascale Challenges) */
 enum { LNV_CANONICAL = 0, LNV_GRAND = 1 };

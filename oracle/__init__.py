@@ -13,9 +13,9 @@ What it computes, and where it comes from:
 * Hotelling's iteration Z <- 2Z - Z S Z for the overlap inverse -- the paper's
   "linear scaling inversion of the overlap matrix" (Development Priorities),
   by the textbook iteration of Hotelling (1943) / Schulz (1933);
-* the inverse square root S^-1/2 (and S^1/2) by the coupled Newton-Schulz
-  iteration (Higham 1997), the companion of that inversion listed as the next
-  step after the hot path;
+* the inverse square root S^-1/2 (and S^1/2) of the same overlap matrix by
+  the coupled Newton-Schulz iteration (Higham 1997), the companion of that
+  inversion for symmetric (Loewdin) orthogonalisation;
 * LNV density-matrix minimisation, K = 3LSL - 2LSLSL -- the paper's linear
   scaling O(N) ground-state solver (Background; Meeting the Exascale
   Challenges), in the non-orthogonal form of Li, Nunes and Vanderbilt (1993)

@@ -157,6 +157,8 @@ EXPORTS = {
     "bsm_batch_destroy": (c_int, [c_void_p]),
     "hotelling_inverse": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                   ctypes.POINTER(_HotParams), ctypes.POINTER(_HotResult)]),
+    "bsm_inverse_sqrt": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                                 ctypes.POINTER(_Matrix), ctypes.POINTER(_HotParams), ctypes.POINTER(_HotResult)]),
     "lnv_state_create": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                  ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix), ctypes.POINTER(_LNVParams),
                                  ctypes.POINTER(c_void_p)]),
@@ -462,6 +464,22 @@ def hotelling_inverse(S: Matrix, Z: Matrix, max_iter: int = 100, tol: float = 1e
     prm = _HotParams(int(max_iter), float(tol), int(init_given))
     res = _HotResult(0, 0, 0.0, ctypes.cast(buf, ctypes.POINTER(c_double)), cap, 0, 0.0, 0)
     code = _lib.hotelling_inverse(Z.pattern.ctx.handle, S.c, Z.c, ctypes.byref(prm), ctypes.byref(res))
+    if code != OK and raise_on_error:
+        _check(code)
+    return HotellingResult(res.status, res.iterations, res.alpha, list(buf[: min(res.n_residuals, cap)]),
+                           res.product_flops, res.start)
+
+
+def inverse_sqrt(S: Matrix, Z: Matrix, Y: Optional[Matrix] = None, max_iter: int = 100, tol: float = 1e-12,
+                 raise_on_error: bool = True) -> HotellingResult:
+    """S^-1/2 into Z (and S^1/2 into Y, on Z's pattern, when given) by the truncated
+    coupled Newton-Schulz iteration; result fields as for hotelling_inverse."""
+    cap = max_iter + 4
+    buf = (c_double * cap)()
+    prm = _HotParams(int(max_iter), float(tol), INIT_PLAIN)
+    res = _HotResult(0, 0, 0.0, ctypes.cast(buf, ctypes.POINTER(c_double)), cap, 0, 0.0, 0)
+    code = _lib.bsm_inverse_sqrt(Z.pattern.ctx.handle, S.c, Z.c, Y.c if Y is not None else None,
+                                 ctypes.byref(prm), ctypes.byref(res))
     if code != OK and raise_on_error:
         _check(code)
     return HotellingResult(res.status, res.iterations, res.alpha, list(buf[: min(res.n_residuals, cap)]),
