@@ -40,12 +40,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="si4096_b9",
-                    choices=["si4096_b9", "si64_b4", "batch64", "si4096_b9_mixed", "guess"],
+                    choices=["si4096_b9", "si64_b4", "batch64", "si4096_b9_mixed", "guess", "invsqrt"],
                     help="batch64: 64 uneven systems (512-4096 atoms, b = 4 and 9), the 16 A x 16 A -> 16 A "
                          "product of each, per-product launches against one tuned persistent launch; "
                          "si4096_b9_mixed: the solve with BF16 then FP32 products and 3 FP64 steps against "
                          "the FP64 solve; guess: networks trained on 512-atom displaced frames, a 4096-atom "
-                         "displaced frame solved from the learned and from the plain starts")
+                         "displaced frame solved from the learned and from the plain starts; invsqrt: "
+                         "truncated S^-1/2 and S^1/2 of the 4096-atom overlap (coupled Newton-Schulz)")
     ap.add_argument("--guess-train", type=int, default=12, help="training frames of the guess workload")
     ap.add_argument("--guess-cells", type=int, default=8, help="cells per side of the guess test frame")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -254,6 +255,75 @@ def mixed_mode(args):
     print(json.dumps(res), flush=True)
 
 
+def invsqrt_mode(args):
+    """S^-1/2 and S^1/2 of the 4096-atom, b = 9 overlap on the 8 A pattern by the truncated
+    coupled Newton-Schulz iteration (bsm_inverse_sqrt), run to its truncation floor."""
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    s = synth.si4096_b9()
+    ctx = bsm.Context(0)
+    pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
+    PS = bsm.Pattern(ctx, pos, s.box, s.cutoffs["S"], s.b)
+    PZ = bsm.Pattern(ctx, pos, s.box, s.cutoffs["Z"], s.b)
+    S, Z, Y = bsm.Matrix(PS), bsm.Matrix(PZ), bsm.Matrix(PZ)
+    bsm.fill_blocks(S, s.S.rows, s.S.cols, s.S.blocks)
+    for _ in range(args.warmup):   # builds the patterns' plans
+        bsm.inverse_sqrt(S, Z, Y, max_iter=100, tol=1e-12)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        r = bsm.inverse_sqrt(S, Z, Y, max_iter=100, tol=1e-12)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    stats = ctx.product_stats()
+    ctx.set_profiling(False)
+    flops = sum(st["flops"] for st in stats) / args.steps
+    top = max(stats, key=lambda st: st["ms"])
+    top_ms = top["ms"] / top["launches"]
+    top_tf = top["flops"] / top["launches"] / (top_ms * 1e-3) / 1e12
+    log(f"[invsqrt] {r.iterations} updates, residual {r.residuals[0]:.3e} -> {r.residuals[-1]:.3e}, "
+        f"{dt:.3f} s, {flops / dt / 1e12:.2f} TFLOP/s over the products")
+    res = {"metric": "s per truncated S^-1/2 (coupled Newton-Schulz), 4096-atom 9-orb", "value": round(dt, 4),
+           "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "si4096_b9 overlap (S on 6 A), S^-1/2 and S^1/2 on 8 A, to the truncation floor",
+                      "natoms": len(s.positions), "orbitals_per_atom": s.b},
+           "updates": r.iterations, "residuals": [r.residuals[0], r.residuals[-1]],
+           "product_gflops": round(flops / dt / 1e9, 1),
+           "roofline": {"bound": "alu", "kernel": f"{kernel_name(top)}: P{top['cutoffs'][0]:g} x "
+                                                  f"P{top['cutoffs'][1]:g} -> P{top['cutoffs'][2]:g}",
+                        "achieved": round(top_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(top_tf / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                        "avg_launch_ms": round(top_ms, 3), "launches": top["launches"]}}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = invsqrt_cpu_baseline(s, r.iterations)
+    print(json.dumps(res), flush=True)
+
+
+def invsqrt_cpu_baseline(s, updates):
+    """The oracle on the same workload (its P(2 r_Z) pattern build included), timed for
+    its start and for 2 updates, and extrapolated linearly to the GPU run's number of
+    updates."""
+    import oracle as O
+    PSo = O.create_pattern(s.positions, s.box, s.cutoffs["S"])
+    So = O.from_blocks(PSo, s.b, s.S.rows, s.S.cols, s.S.blocks)
+    PZo = O.create_pattern(s.positions, s.box, s.cutoffs["Z"])
+    t = time.perf_counter()
+    O.inverse_sqrt(So, PZo, max_iter=0, tol=0.0)
+    t0 = time.perf_counter() - t
+    t = time.perf_counter()
+    O.inverse_sqrt(So, PZo, max_iter=2, tol=0.0)
+    t2 = time.perf_counter() - t
+    per = (t2 - t0) / 2
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    return {"value": round(t0 + updates * per, 2), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"the same {len(s.positions)}-atom workload: start {t0:.1f} s and 2 updates {t2 - t0:.1f} s timed, "
+                      f"extrapolated to {updates} updates"}
+
+
 def guess_mode(args):
     """Learned starts: train on 512-atom displaced frames, solve a larger held-out frame both ways."""
     import torch
@@ -378,6 +448,9 @@ def main():
         return
     if args.workload == "guess":
         guess_mode(args)
+        return
+    if args.workload == "invsqrt":
+        invsqrt_mode(args)
         return
     s = synth.si4096_b9() if args.workload == "si4096_b9" else synth.si64_b4()
     cut = s.cutoffs
