@@ -402,8 +402,8 @@ def kernel_sources_sha() -> str:
 
 def kernel_name(st) -> str:
     b, g, v, p = st["b"], st["rows"], st["variant"], st.get("precision", 0)
-    if p == 2 and b == 9 and g == 4 and v in (3, 4):
-        return "k_product_mfma_bf16<9, 4>"
+    if p == 2 and b == 9 and g in (4, 8) and v in (3, 4):
+        return f"k_product_mfma_bf16<{g}>"
     depth = 3 if v == 3 and g <= 4 else 2   # 8-row ring tiles run 1 entry ahead in both ring variants
     name = {0: f"k_product_sgpr<{b}, {g}>", 1: f"k_product_f64_dpp<{b}, {g}>", 2: f"k_product_wg<{b}>",
             3: f"k_product_ring<{b}, {g}, {depth}>", 4: f"k_product_ring<{b}, {g}, 2>"}.get(v, f"variant {v}")

@@ -141,17 +141,18 @@ __global__ void k_pack_bf16_blocks(int64_t nblk, const double *__restrict__ x, u
     y[e] = v;
 }
 
-// BF16 matrix-core product tiles (b = 9, 4-row wave tiles), one per one-wave workgroup.
+// BF16 matrix-core product tiles (b = 9, G-row wave tiles), one per one-wave workgroup.
+template <int G>
 __global__ __launch_bounds__(64) void k_product_mfma_bf16(
     int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
     const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const unsigned short *__restrict__ pA,
     const unsigned short *__restrict__ pBt, const unsigned short *__restrict__ pz, double *__restrict__ vC,
     double alpha, double beta)
 {
-    __shared__ __attribute__((aligned(16))) char ring[4 * 11 * kPackedBytes];
+    __shared__ __attribute__((aligned(16))) char ring[4 * (G + 7) * kPackedBytes];
     const int64_t t = logical_workgroup(nwg_padded);
     if (t >= ntiles) return;
-    tile_mfma_bf16(order[t], hdr, ebeg, ent, pA, pBt, pz, vC, alpha, beta, (lds_char_t *)ring);
+    tile_mfma_bf16<G>(order[t], hdr, ebeg, ent, pA, pBt, pz, vC, alpha, beta, (lds_char_t *)ring);
 }
 
 // ---------------------------------------------------------------- planner
@@ -590,11 +591,8 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     if (plan->G > 8) plan = get_plan_kind(ctx, PA, PB, PC, 0, default_rows_per_wave(PC->b));   // wave tiles
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
-    // BF16, b = 9: matrix cores over 4-row tiles (the default rows per tile of the ring is 8)
-    if (prec == BSM_BF16 && PC->b == 9 && plan->G == 8 && ctx->rows_per_wave == 0 &&
-        (plan->variant == 3 || plan->variant == 4))
-        plan = get_plan_kind(ctx, PA, PB, PC, plan->variant, 4);
-    if (prec == BSM_BF16 && PC->b == 9 && plan->G == 4 && (plan->variant == 3 || plan->variant == 4)) {
+    if (prec == BSM_BF16 && PC->b == 9 && (plan->G == 4 || plan->G == 8) &&
+        (plan->variant == 3 || plan->variant == 4)) {
         // matrix cores: operands packed to BF16 (B transposed), FP32 accumulation
         unsigned short *pa = reinterpret_cast<unsigned short *>(ctx->scratch_f32(0, PA->nnzb * (kPackedBlock / 2)));
         unsigned short *pb = reinterpret_cast<unsigned short *>(ctx->scratch_f32(1, PB->nnzb * (kPackedBlock / 2)));
@@ -607,9 +605,14 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
             BSM_HIP_TRY(hipEventRecord(rec.start, st));
         }
         const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
-        k_product_mfma_bf16<<<(unsigned)nwg_padded, 64, 0, st>>>(
-            plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
-            plan->ent.as<int>(), pa, pb, ctx->zero_block.as<unsigned short>(), C, alpha, beta);
+        if (plan->G == 8)
+            k_product_mfma_bf16<8><<<(unsigned)nwg_padded, 64, 0, st>>>(
+                plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+                plan->ent.as<int>(), pa, pb, ctx->zero_block.as<unsigned short>(), C, alpha, beta);
+        else
+            k_product_mfma_bf16<4><<<(unsigned)nwg_padded, 64, 0, st>>>(
+                plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+                plan->ent.as<int>(), pa, pb, ctx->zero_block.as<unsigned short>(), C, alpha, beta);
         BSM_HIP_TRY(hipGetLastError());
         if (ctx->profiling) {
             BSM_HIP_TRY(hipEventRecord(rec.stop, st));

@@ -729,14 +729,14 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
 }
 
 // ---------------------------------------------------------------- BF16 matrix-core tiles (b = 9)
-// The same tiles (4 rows x 7 columns of 9 x 9 blocks) computed on the matrix
-// cores with v_mfma_f32_16x16x32_bf16.  Operands are pre-packed in BF16: every
+// The same tiles (G = 4 or 8 rows x 7 columns of 9 x 9 blocks) computed on the
+// matrix cores with v_mfma_f32_16x16x32_bf16.  Operands are pre-packed in BF16: every
 // A block as 9 rows of 16 (the contraction index m = 0..8 then 7 zeros),
 // every B block transposed the same way (row q holds B[m][q]), 288 bytes per
 // block, so each MFMA operand of a lane is one aligned 16-byte LDS read.  Two
 // consecutive entries form the K = 32 of one MFMA (16 per entry, 9 of them
-// live).  The tile's 36 output rows are 3 MFMA row tiles (48 rows, the last 12
-// padding), its 63 output columns 4 column tiles (64 columns).  Absent A or B
+// live).  The tile's 9 G output rows are ceil(9 G / 16) MFMA row tiles (48 rows for
+// 36, 80 for 72: the rest padding), its 63 output columns 4 column tiles (64).  Absent A or B
 // blocks are staged from a packed zero block.  Entries are copied into a
 // per-wave LDS ring of four slots by one 16-byte LDS-DMA per block (18 lanes),
 // one entry pair ahead of the multiply.  Products are exact in FP32 and summed
@@ -747,12 +747,14 @@ constexpr int kPackedBytes = kPackedBlock * 2;   // 288
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
+template <int G>
 __device__ inline void tile_mfma_bf16(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
                                       const int *__restrict__ ent, const unsigned short *__restrict__ pA,
                                       const unsigned short *__restrict__ pBt, const unsigned short *__restrict__ pz,
                                       double *__restrict__ vC, double alpha, double beta, lds_char_t *ring)
 {
-    constexpr int B = 9, G = 4, JT = 7, BB = 81;
+    constexpr int B = 9, JT = 7, BB = 81;
+    constexpr int ROWS = 9 * G, RT = (ROWS + 15) / 16;   // output rows, MFMA row tiles
     constexpr int HS = G + G * JT, ES = G + JT, NB = G + JT;
     constexpr int SLOT = NB * kPackedBytes;          // bytes per ring slot (one entry)
     constexpr int NI = NB;                           // DMA loads per entry
@@ -768,20 +770,20 @@ __device__ inline void tile_mfma_bf16(int64_t tile, const int *__restrict__ hdr,
     const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
 
     // LDS byte offsets of this lane's operands inside a slot (-1: padding row / column)
-    int aoff[3], boff[4];
+    int aoff[RT], boff[4];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < RT; ++t) {
         const int r = 16 * t + l16;
-        aoff[t] = r < 36 ? (r / 9) * kPackedBytes + (r % 9) * 32 + half * 16 : -1;
+        aoff[t] = r < ROWS ? (r / 9) * kPackedBytes + (r % 9) * 32 + half * 16 : -1;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int cc = 16 * u + l16;
         boff[u] = cc < 63 ? (G + cc / 9) * kPackedBytes + (cc % 9) * 32 + half * 16 : -1;
     }
-    f32x4_t acc[3][4];
+    f32x4_t acc[RT][4];
 #pragma unroll
-    for (int t = 0; t < 3; ++t)
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[t][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
@@ -813,15 +815,15 @@ __device__ inline void tile_mfma_bf16(int64_t tile, const int *__restrict__ hdr,
     // the pair of entries in slots (P, P + 1)
     auto compute = [&](auto P) {
         const lds_char_t *slot = ring + (decltype(P)::value + e_of_lane) * SLOT;
-        bf16x8_t av[3], bv[4];
+        bf16x8_t av[RT], bv[4];
 #pragma unroll
-        for (int t = 0; t < 3; ++t)
+        for (int t = 0; t < RT; ++t)
             av[t] = aoff[t] >= 0 ? *(const __attribute__((address_space(3))) bf16x8_t *)(slot + aoff[t]) : zero8();
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             bv[u] = boff[u] >= 0 ? *(const __attribute__((address_space(3))) bf16x8_t *)(slot + boff[u]) : zero8();
 #pragma unroll
-        for (int t = 0; t < 3; ++t)
+        for (int t = 0; t < RT; ++t)
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], bv[u], acc[t][u], 0, 0, 0);
@@ -856,11 +858,11 @@ __device__ inline void tile_mfma_bf16(int64_t tile, const int *__restrict__ hdr,
         if (cc >= 63) continue;
         const int jj = cc / 9, q = cc % 9;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
+        for (int t = 0; t < RT; ++t) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = 16 * t + 4 * g + i;
-                if (r >= 36) continue;
+                if (r >= ROWS) continue;
                 const int a = r / 9, p = r % 9;
                 const int cs = h[G + a * JT + jj];
                 if (cs < 0) continue;
