@@ -141,18 +141,20 @@ __global__ void k_pack_bf16_blocks(int64_t nblk, const double *__restrict__ x, u
     y[e] = v;
 }
 
-// BF16 matrix-core product tiles (b = 9, G-row wave tiles), one per one-wave workgroup.
-template <int G>
+// BF16 matrix-core product tiles (b = 9, G-row wave tiles), one per one-wave workgroup
+// (BUF: packed operands copied through buffer resources of a_bytes and b_bytes).
+template <int G, bool BUF>
 __global__ __launch_bounds__(64) void k_product_mfma_bf16(
     int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
     const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const unsigned short *__restrict__ pA,
     const unsigned short *__restrict__ pBt, const unsigned short *__restrict__ pz, double *__restrict__ vC,
-    double alpha, double beta)
+    double alpha, double beta, unsigned a_bytes, unsigned b_bytes)
 {
     __shared__ __attribute__((aligned(16))) char ring[4 * (G + 7) * kPackedBytes];
     const int64_t t = logical_workgroup(nwg_padded);
     if (t >= ntiles) return;
-    tile_mfma_bf16<G>(order[t], hdr, ebeg, ent, pA, pBt, pz, vC, alpha, beta, (lds_char_t *)ring);
+    tile_mfma_bf16<G, BUF>(order[t], hdr, ebeg, ent, pA, pBt, pz, vC, alpha, beta, (lds_char_t *)ring, a_bytes,
+                           b_bytes);
 }
 
 // ---------------------------------------------------------------- planner
@@ -605,14 +607,20 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
             BSM_HIP_TRY(hipEventRecord(rec.start, st));
         }
         const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
+        // variant 4: buffer copies while the packed operands fit a buffer resource
+        const int64_t ab = PA->nnzb * (int64_t)kPackedBytes, bb = PB->nnzb * (int64_t)kPackedBytes;
+        const bool buf = plan->variant == 4 && ab <= (int64_t)kBufMaxBytes && bb <= (int64_t)kBufMaxBytes;
+        auto go = [&](auto kern) {
+            kern<<<(unsigned)nwg_padded, 64, 0, st>>>(plan->ntiles, nwg_padded, plan->order.as<int>(),
+                                                      plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+                                                      plan->ent.as<int>(), pa, pb,
+                                                      ctx->zero_block.as<unsigned short>(), C, alpha, beta,
+                                                      buf ? (unsigned)ab : 0u, buf ? (unsigned)bb : 0u);
+        };
         if (plan->G == 8)
-            k_product_mfma_bf16<8><<<(unsigned)nwg_padded, 64, 0, st>>>(
-                plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
-                plan->ent.as<int>(), pa, pb, ctx->zero_block.as<unsigned short>(), C, alpha, beta);
+            buf ? go(k_product_mfma_bf16<8, true>) : go(k_product_mfma_bf16<8, false>);
         else
-            k_product_mfma_bf16<4><<<(unsigned)nwg_padded, 64, 0, st>>>(
-                plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
-                plan->ent.as<int>(), pa, pb, ctx->zero_block.as<unsigned short>(), C, alpha, beta);
+            buf ? go(k_product_mfma_bf16<4, true>) : go(k_product_mfma_bf16<4, false>);
         BSM_HIP_TRY(hipGetLastError());
         if (ctx->profiling) {
             BSM_HIP_TRY(hipEventRecord(rec.stop, st));

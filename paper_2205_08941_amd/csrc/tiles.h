@@ -747,11 +747,14 @@ constexpr int kPackedBytes = kPackedBlock * 2;   // 288
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-template <int G>
+// BUF: copies through buffer resources over the packed operands (a_bytes,
+// b_bytes at most kBufMaxBytes); absent blocks read zeros past the resource.
+template <int G, bool BUF = false>
 __device__ inline void tile_mfma_bf16(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
                                       const int *__restrict__ ent, const unsigned short *__restrict__ pA,
                                       const unsigned short *__restrict__ pBt, const unsigned short *__restrict__ pz,
-                                      double *__restrict__ vC, double alpha, double beta, lds_char_t *ring)
+                                      double *__restrict__ vC, double alpha, double beta, lds_char_t *ring,
+                                      unsigned a_bytes = 0, unsigned b_bytes = 0)
 {
     constexpr int B = 9, JT = 7, BB = 81;
     constexpr int ROWS = 9 * G, RT = (ROWS + 15) / 16;   // output rows, MFMA row tiles
@@ -787,12 +790,25 @@ __device__ inline void tile_mfma_bf16(int64_t tile, const int *__restrict__ hdr,
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[t][u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
+    const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc((void *)pA, 0, (int)a_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc((void *)pBt, 0, (int)b_bytes, 0x00020000);
     // copy entry q into ring slot P (18 lanes x 16 bytes per block)
     auto issue = [&](auto P, int q) {
         lds_char_t *slot = ring + decltype(P)::value * SLOT;
         int sl[NB];
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) sl[blk] = entu[(int64_t)q * ES + blk];
+        if constexpr (BUF) {
+            // one lane mask for the entry; slot -1 gives offset 2^32 - 288, past the resource
+            if (lane < kPackedBytes / 16) {
+#pragma unroll
+                for (int blk = 0; blk < NB; ++blk)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        blk < G ? rsA : rsB, (lds_void_t *)(slot + blk * kPackedBytes), 16,
+                        (unsigned)sl[blk] * (unsigned)kPackedBytes + 16u * (unsigned)lane, 0, 0, 0);
+            }
+            return;
+        }
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) {
             const unsigned short *src =
