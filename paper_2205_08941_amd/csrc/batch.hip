@@ -36,6 +36,7 @@ constexpr int kBatchRows = 8;   // rows per tile (the separate launches' default
 struct BatchDesc {
     int kind;
     int pad;
+    unsigned a_bytes, b_bytes;   // operand sizes (buffer copies)
     const int *hdr;
     const int64_t *ebeg;
     const int *ent;
@@ -55,8 +56,10 @@ __global__ void k_zero_counters(int n, unsigned *c)
 }
 
 // One kernel per batch precision (F64 = true: FP64 operands; false: FP32),
-// so that each is compiled with the registers its own tiles need.
-template <bool F64>
+// so that each is compiled with the registers its own tiles need.  BUF: every
+// product's operands fit buffer resources (a_bytes, b_bytes), and the tiles
+// copy through them.
+template <bool F64, bool BUF>
 __global__ __launch_bounds__(64) void k_product_batch(const BatchDesc *__restrict__ desc, const int2 *__restrict__ items,
                                                       const int64_t *__restrict__ qbeg, int nq,
                                                       unsigned *__restrict__ counters, const double *__restrict__ zblk)
@@ -81,22 +84,22 @@ __global__ __launch_bounds__(64) void k_product_batch(const BatchDesc *__restric
         const int kind = __builtin_amdgcn_readfirstlane(d.kind);
         if constexpr (F64) {
             if (kind == kKindF64Ring9)
-                tile_ring<9, kBatchRows, kBatchRing, double>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A,
+                tile_ring<9, kBatchRows, kBatchRing, double, BUF>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A,
                                                              (const double *)d.B, zblk, d.C, d.alpha, d.beta,
-                                                             (lds_char_t *)ring);
+                                                             (lds_char_t *)ring, d.a_bytes, d.b_bytes);
             else
-                tile_ring<4, kBatchRows, kBatchRing, double>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A,
+                tile_ring<4, kBatchRows, kBatchRing, double, BUF>(it.y, d.hdr, d.ebeg, d.ent, (const double *)d.A,
                                                              (const double *)d.B, zblk, d.C, d.alpha, d.beta,
-                                                             (lds_char_t *)ring);
+                                                             (lds_char_t *)ring, d.a_bytes, d.b_bytes);
         } else {
             if (kind == kKindF32Ring9)
-                tile_ring<9, kBatchRows, kBatchRing, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A,
+                tile_ring<9, kBatchRows, kBatchRing, float, BUF>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A,
                                                             (const float *)d.B, (const float *)zblk, d.C, d.alpha,
-                                                            d.beta, (lds_char_t *)ring);
+                                                            d.beta, (lds_char_t *)ring, d.a_bytes, d.b_bytes);
             else
-                tile_ring<4, kBatchRows, kBatchRing, float>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A,
+                tile_ring<4, kBatchRows, kBatchRing, float, BUF>(it.y, d.hdr, d.ebeg, d.ent, (const float *)d.A,
                                                             (const float *)d.B, (const float *)zblk, d.C, d.alpha,
-                                                            d.beta, (lds_char_t *)ring);
+                                                            d.beta, (lds_char_t *)ring, d.a_bytes, d.b_bytes);
         }
     }
 }
@@ -139,6 +142,7 @@ struct bsm_batch_s {
     DevBuf desc, items, qbeg, counters;
     double flops = 0.0;
     int64_t ntiles = 0;
+    bool buf = true;          // every product's operands fit buffer resources
     bool tuned = false;
     bsm_batch_config best{};
     bsm_batch_config built{-1, -1, -1};
@@ -222,12 +226,14 @@ void bsm_batch_s::run(const bsm_batch_config &cfg)
     }
     k_zero_counters<<<1, 64, 0, st>>>(cfg.queues, counters.as<unsigned>());
     const int blocks = kCUs * cfg.waves_per_cu;   // one wave each
+    auto go = [&](auto kern) {
+        kern<<<blocks, 64, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(), cfg.queues,
+                                    counters.as<unsigned>(), c->zero_block.as<double>());
+    };
     if (prec == BSM_F64)
-        k_product_batch<true><<<blocks, 64, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(),
-                                                      cfg.queues, counters.as<unsigned>(), c->zero_block.as<double>());
+        buf ? go(k_product_batch<true, true>) : go(k_product_batch<true, false>);
     else
-        k_product_batch<false><<<blocks, 64, 0, st>>>(desc.as<BatchDesc>(), items.as<int2>(), qbeg.as<int64_t>(),
-                                                       cfg.queues, counters.as<unsigned>(), c->zero_block.as<double>());
+        buf ? go(k_product_batch<false, true>) : go(k_product_batch<false, false>);
     BSM_HIP_TRY(hipGetLastError());
 }
 
@@ -298,6 +304,12 @@ int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *
             x.A = bt->a32.back().ptr;
             x.B = bt->b32.back().ptr;
         }
+        const int64_t esz = precision == BSM_F64 ? 8 : 4;
+        const int64_t ab = esz * bt->a_n.back(), bb = esz * bt->b_n.back();
+        if (ab > (int64_t)kBufMaxBytes || bb > (int64_t)kBufMaxBytes || (((uintptr_t)x.A | (uintptr_t)x.B) & 15))
+            bt->buf = false;
+        x.a_bytes = (unsigned)std::min<int64_t>(ab, kBufMaxBytes);
+        x.b_bytes = (unsigned)std::min<int64_t>(bb, kBufMaxBytes);
     }
     bt->desc = DevBuf(c, sizeof(BatchDesc) * n);
     BSM_HIP_TRY(hipMemcpy(bt->desc.ptr, d.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice));
