@@ -23,7 +23,7 @@ Conventions
 from __future__ import annotations
 
 import dataclasses
-from typing import Dict, Tuple
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -97,6 +97,10 @@ class SiliconSystem:
     n_electrons: float           # 4 valence electrons per Si atom
     cutoffs: Dict[str, float]    # {"S","H","L","Z"} in Angstrom
     seed: int
+    # derivatives (smooth systems, derivatives=True): dS[c] and dH[c] hold, block by block
+    # on the S and H block lists, d S_ij / d R_j^c (= -d S_ij / d R_i^c for i != j; 0 for i == j)
+    dS: Optional[List[BlockList]] = None
+    dH: Optional[List[BlockList]] = None
 
     @property
     def natoms(self) -> int:
@@ -217,9 +221,24 @@ def _pair_vectors(pos, box, i, j, sh, d):
     return (pos[j] + sh * box - pos[i]) / d[:, None]
 
 
+def _smooth_pair_derivative(coef, pos, box, i, j, sh, d):
+    """d/dr_c of exp(-d / S_DECAY) U(r_hat) at the pair vector r (= r_j + shift box - r_i),
+    shape (n, 3, b, b): the radial factor's derivative times U plus the angular part,
+    dU/dr_hat_e (delta_ec - r_hat_e r_hat_c) / d."""
+    _, C1, C2 = coef
+    rh = _pair_vectors(pos, box, i, j, sh, d)
+    U = _smooth_blocks(coef, rh)
+    dU = 0.25 * (C1[None] + 2.0 * np.einsum("abef,nf->nabe", C2, rh))
+    proj = (np.eye(3)[None] - rh[:, :, None] * rh[:, None, :]) / d[:, None, None]
+    g = np.einsum("nabe,nec->ncab", dU, proj) - (rh / S_DECAY)[:, :, None, None] * U[:, None]
+    return np.exp(-d / S_DECAY)[:, None, None, None] * g
+
+
 def make_system(name: str, ncell, b: int, cutoffs: Dict[str, float], seed: int,
                 displacement_sigma: float = 0.0, s_amp: float = S_AMP,
-                h_random: bool = True, smooth: bool = False) -> SiliconSystem:
+                h_random: bool = True, smooth: bool = False,
+                extra_displacement: Optional[np.ndarray] = None,
+                derivatives: bool = False) -> SiliconSystem:
     """Diamond-Si system with seeded S and gapped tight-binding-like H.
 
     S: identity on site; off site exp(-d/1.5 A) * U, U uniform in [-0.3, 0.3],
@@ -239,6 +258,11 @@ def make_system(name: str, ncell, b: int, cutoffs: Dict[str, float], seed: int,
     seeded orbital-pair functions of the bond direction (_smooth_coefficients),
     the on-site part of V_rand is one seeded symmetric block shared by all
     atoms, and the V_rand scale is fixed on the undisplaced lattice.
+
+    extra_displacement (N, 3) is added to the positions after the seeded
+    displacements (finite differences); derivatives = True (smooth only) also
+    returns the derivative blocks dS, dH of every S and H block with respect to
+    its column atom's position.
     """
     ncell = (ncell,) * 3 if np.isscalar(ncell) else tuple(ncell)
     ideal, box, sub = diamond_positions(ncell)
@@ -252,7 +276,11 @@ def make_system(name: str, ncell, b: int, cutoffs: Dict[str, float], seed: int,
         u2 = counter_uniform(seed, STREAM_DISP, idx, comp, 1)
         gauss = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2 * np.pi * u2)
         pos = pos + displacement_sigma * gauss
+    if extra_displacement is not None:
+        pos = pos + np.asarray(extra_displacement, float)
     pos = np.mod(pos, box)
+    if derivatives and not smooth:
+        raise ValueError("derivative blocks need the geometry-smooth generator (smooth=True)")
 
     rS, rH = cutoffs["S"], cutoffs["H"]
     rmax = max(rS, rH)
@@ -314,8 +342,28 @@ def make_system(name: str, ncell, b: int, cutoffs: Dict[str, float], seed: int,
     H = BlockList(*_fold(np.concatenate([ri, bi.astype(np.int32), diag]),
                          np.concatenate([rj, bj.astype(np.int32), diag]),
                          np.concatenate([Vr, Vb, Vd]), natoms))
+    dS = dH = None
+    if derivatives:
+        # the same folds as S and H with derivative blocks in place of the blocks (zero for the
+        # geometry-independent parts and for images of an atom with itself)
+        zero = np.zeros((natoms, b, b))
+        gS = s_amp * _smooth_pair_derivative(_smooth_coefficients(seed, STREAM_S, b), pos, box,
+                                             i[inS], j[inS], sh[inS], d[inS])
+        gS[i[inS] == j[inS]] = 0.0
+        gH = _smooth_pair_derivative(coefH, pos, box, i[inH], j[inH], sh[inH], d[inH])
+        gH[i[inH] == j[inH]] = 0.0
+        scale = (0.5 * T_BOND) / rowsum.max() if h_random else 0.0
+        dS, dH = [], []
+        for c in range(3):
+            dS.append(BlockList(*_fold(np.concatenate([diag, i[inS]]), np.concatenate([diag, j[inS]]),
+                                       np.concatenate([zero, gS[:, c]]), natoms)))
+            hr, hc, hv = _fold(np.concatenate([diag, i[inH]]), np.concatenate([diag, j[inH]]),
+                               np.concatenate([zero, scale * gH[:, c]]), natoms)
+            dH.append(BlockList(*_fold(np.concatenate([hr, bi.astype(np.int32), diag]),
+                                       np.concatenate([hc, bj.astype(np.int32), diag]),
+                                       np.concatenate([hv, np.zeros_like(Vb), zero]), natoms)))
     return SiliconSystem(name=name, positions=pos, box=box, b=b, S=S, H=H,
-                         n_electrons=4.0 * natoms, cutoffs=dict(cutoffs), seed=seed)
+                         n_electrons=4.0 * natoms, cutoffs=dict(cutoffs), seed=seed, dS=dS, dH=dH)
 
 
 # ---------------------------------------------------------------------------

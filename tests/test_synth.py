@@ -43,3 +43,24 @@ def test_counter_uniform_range():
     u = synth.counter_uniform(1, 2, np.arange(100000))
     assert u.min() >= 0 and u.max() < 1
     assert abs(u.mean() - 0.5) < 0.01
+
+
+def test_smooth_derivative_blocks_match_finite_differences():
+    # dS, dH hold d(block ij)/dR_j (and -d/dR_i); central differences of the
+    # generator itself, moving one atom, agree to rounding.
+    kw = dict(displacement_sigma=0.05, smooth=True)
+    s = synth.make_system("f", 2, 4, synth.SMALL_CUTOFFS, 11, derivatives=True, **kw)
+    J, h = 5, 1e-5
+    for c in range(3):
+        e = np.zeros((s.natoms, 3))
+        e[J, c] = h
+        p = synth.make_system("f", 2, 4, synth.SMALL_CUTOFFS, 11, extra_displacement=e, **kw)
+        m = synth.make_system("f", 2, 4, synth.SMALL_CUTOFFS, 11, extra_displacement=-e, **kw)
+        for name in ("S", "H"):
+            D = getattr(s, "d" + name)[c]
+            assert np.array_equal(D.rows, getattr(s, name).rows) and np.array_equal(D.cols, getattr(s, name).cols)
+            fd = (getattr(p, name).blocks - getattr(m, name).blocks) / (2 * h)
+            want = np.zeros_like(fd)
+            col, row = (D.cols == J) & (D.rows != J), (D.rows == J) & (D.cols != J)
+            want[col], want[row] = D.blocks[col], -D.blocks[row]
+            assert np.abs(fd - want).max() < 1e-9 * max(1.0, np.abs(want).max())
