@@ -16,6 +16,8 @@ What it computes, and where it comes from:
 * the inverse square root S^-1/2 (and S^1/2) of the same overlap matrix by
   the coupled Newton-Schulz iteration (Higham 1997), the companion of that
   inversion for symmetric (Loewdin) orthogonalisation;
+* forces -dOmega/dR at the converged density matrix (Hellmann-Feynman and
+  energy-density-matrix terms), from derivative blocks of S and H;
 * LNV density-matrix minimisation, K = 3LSL - 2LSLSL -- the paper's linear
   scaling O(N) ground-state solver (Background; Meeting the Exascale
   Challenges), in the non-orthogonal form of Li, Nunes and Vanderbilt (1993)
@@ -709,3 +711,53 @@ def density_matrix(st: LNVState, pattern: Pattern) -> Matrix:
     K = product(X, st.L, pattern)
     K2 = product(W, st.L, pattern)
     return Matrix(pattern, st.L.b, 3.0 * K.blocks - 2.0 * K2.blocks)
+
+
+# ---------------------------------------------------------------------------
+# Forces from the converged density matrix
+# ---------------------------------------------------------------------------
+def lnv_chemical_potential(st: LNVState) -> float:
+    """mu = <G_N, M(G_E)> / <G_N, M(G_N)> at the current L (the canonical definition)."""
+    X, Y, W, U, E, N = lnv_energy_terms(st)
+    GE, GN = lnv_gradients(st, X, W, U)
+    PE, PN = _precondition(st, GE), _precondition(st, GN)
+    return dot(GN, PE) / dot(GN, PN)
+
+
+def lnv_forces(st: LNVState, dS: List[Matrix], dH: List[Matrix]) -> np.ndarray:
+    """Forces F_I = -d Omega / d R_I at a converged L, Omega = E - mu (N - N_e).
+
+    The paper lists forces with the solver's next capabilities; this is the
+    standard derivative of the density-matrix functional.  At a stationary L
+    (G_E = mu G_N on P_L) dE/dR = dOmega/dR at fixed L.  With K = 3LSL - 2LSLSL,
+    H' = H - mu S and the energy-density matrix Q = 3 L H' L - 2 (LSL H' L + L H' LSL),
+        dOmega = 2 Tr[K dH] + 2 Tr[(Q - mu K) dS].
+    dS and dH hold, for every block (i, j) of S and H, d(block)/dR_j per Cartesian
+    direction (d/dR_i is its negative; blocks of an atom with itself do not move),
+    so with K, Q symmetric the derivative with respect to atom I collapses onto its
+    row:  F_I^c = 4 sum_{j != I} <K_Ij, dH^c_Ij> + <(Q - mu K)_Ij, dS^c_Ij>  (elementwise).
+    Needs r_S == r_H.  Q is exact on P_S: L H' on P(r_L + r_S), M = L H' L on
+    P(2 r_L + r_S), X M with X = L S masked to P_S.
+    """
+    S, H, L = st.S, st.H, st.L
+    PS = S.pattern
+    assert abs(PS.cutoff - H.pattern.cutoff) < 1e-12, "forces need the S and H patterns equal"
+    b = S.b
+    mu = lnv_chemical_potential(st)
+    K = density_matrix(st, PS)
+    Hp = Matrix(PS, b, H.blocks - mu * S.blocks)
+    X = product(L, S, st.PX)
+    LH = product(L, Hp, st.PX)
+    PM = derived_pattern(L.pattern, 2.0 * L.pattern.cutoff + PS.cutoff)
+    M = product(LH, L, PM)
+    XM = product(X, M, PS)
+    Q = Matrix(PS, b, 3.0 * mask_copy(M, PS).blocks - 2.0 * (XM.blocks + transpose(XM).blocks))
+    Wt = Q.blocks - mu * K.blocks
+    rows = PS.rows()
+    off = rows != PS.cols
+    F = np.zeros((PS.natoms, 3))
+    for c in range(3):
+        per_block = (np.einsum("nab,nab->n", K.blocks, dH[c].blocks) +
+                     np.einsum("nab,nab->n", Wt, dS[c].blocks))
+        np.add.at(F[:, c], rows[off], 4.0 * per_block[off])
+    return F
