@@ -365,6 +365,21 @@ int lnv_state_destroy(lnv_state *st);
  * (harmless: every step recomputes it).  Synchronises. */
 int lnv_idempotency_error(lnv_state *st, double *e_idem);
 
+/* Forces at the current L (meant for a converged L: the paper lists forces with
+ * the solver's next capabilities; the standard derivative of the density-matrix
+ * functional): F_I = -d Omega / d R_I, Omega = E - mu (N - N_e), at fixed L,
+ *     F_I^c = 4 sum_{j != I} <K_Ij, dH^c_Ij> + <(Q - mu K)_Ij, dS^c_Ij>   (elementwise)
+ * with K = 3LSL - 2LSLSL, H' = H - mu S and the energy-density matrix
+ * Q = 3 L H' L - 2 (LSL H' L + L H' LSL), both on P_S, and mu from the current
+ * gradients (<G_N, M(G_E)> / <G_N, M(G_N)>; the state's mu in LNV_GRAND mode).
+ * dS and dH are arrays of 3 matrices (x, y, z) on the state's S and H pattern
+ * objects holding, for every block (i, j), d(block)/dR_j (d/dR_i is its negative;
+ * diagonal blocks are ignored).  S and H must share one pattern range.  forces:
+ * host, natoms x 3 doubles (caller-owned); mu: optional host output.  FP64
+ * products; overwrites the state's P_X scratch (every step recomputes it).
+ * Synchronises.  Errors: BSM_EPATTERN (derivative patterns), BSM_ENONFINITE. */
+int lnv_forces(lnv_state *st, const bsm_matrix *dS, const bsm_matrix *dH, double *forces, double *mu);
+
 /* A precision schedule for a whole solve (an extension built on the method: low-precision
  * products with FP64 traces, then FP64 refinement).  Stage s runs lnv_step with
  * products in precision[s] until |dE| < tol_E[s] (tol_E[s] > 0), or, when

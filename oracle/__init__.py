@@ -736,8 +736,9 @@ def lnv_forces(st: LNVState, dS: List[Matrix], dH: List[Matrix]) -> np.ndarray:
     direction (d/dR_i is its negative; blocks of an atom with itself do not move),
     so with K, Q symmetric the derivative with respect to atom I collapses onto its
     row:  F_I^c = 4 sum_{j != I} <K_Ij, dH^c_Ij> + <(Q - mu K)_Ij, dS^c_Ij>  (elementwise).
-    Needs r_S == r_H.  Q is exact on P_S: L H' on P(r_L + r_S), M = L H' L on
-    P(2 r_L + r_S), X M with X = L S masked to P_S.
+    Needs r_S == r_H.  Q is exact on P_S: L H' on P_X = P(r_L + r_S), M = L H' L
+    on P(r_X + r_S) (all that X M reads for outputs on P_S), X M with X = L S
+    masked to P_S.
     """
     S, H, L = st.S, st.H, st.L
     PS = S.pattern
@@ -748,7 +749,7 @@ def lnv_forces(st: LNVState, dS: List[Matrix], dH: List[Matrix]) -> np.ndarray:
     Hp = Matrix(PS, b, H.blocks - mu * S.blocks)
     X = product(L, S, st.PX)
     LH = product(L, Hp, st.PX)
-    PM = derived_pattern(L.pattern, 2.0 * L.pattern.cutoff + PS.cutoff)
+    PM = derived_pattern(L.pattern, st.PX.cutoff + PS.cutoff)
     M = product(LH, L, PM)
     XM = product(X, M, PS)
     Q = Matrix(PS, b, 3.0 * mask_copy(M, PS).blocks - 2.0 * (XM.blocks + transpose(XM).blocks))

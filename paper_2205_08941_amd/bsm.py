@@ -167,6 +167,8 @@ EXPORTS = {
     "lnv_state_reset": (c_int, [c_void_p, ctypes.POINTER(_LNVParams), ctypes.POINTER(c_double)]),
     "lnv_solve": (c_int, [c_void_p, ctypes.POINTER(_LNVSchedule), ctypes.POINTER(_LNVSolveResult)]),
     "lnv_idempotency_error": (c_int, [c_void_p, ctypes.POINTER(c_double)]),
+    "lnv_forces": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                           ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
     # learned initial guess (include/bsm_guess.h)
     "bsm_mlp_param_count": (c_int64, [ctypes.POINTER(_MlpShape)]),
     "bsm_mlp_create": (c_int, [c_void_p, ctypes.POINTER(_MlpShape), c_void_p, ctypes.POINTER(c_void_p)]),
@@ -550,6 +552,18 @@ class LNV:
         e = c_double()
         _check(_lib.lnv_idempotency_error(self.handle, ctypes.byref(e)))
         return e.value
+
+    def forces(self, dS: Sequence[Matrix], dH: Sequence[Matrix]):
+        """(forces (natoms, 3) as numpy, mu) at the current L; dS, dH: the x, y, z derivative
+        matrices on S's and H's patterns (d block_ij / d R_j)."""
+        assert len(dS) == 3 and len(dH) == 3
+        ms = (_Matrix * 3)(*[m._c for m in dS])
+        mh = (_Matrix * 3)(*[m._c for m in dH])
+        n = self.S.pattern.natoms
+        out = (c_double * (3 * n))()
+        mu = c_double()
+        _check(_lib.lnv_forces(self.handle, ms, mh, out, ctypes.byref(mu)))
+        return np.frombuffer(out, dtype=np.float64).reshape(n, 3).copy(), mu.value
 
     def solve(self, stages) -> dict:
         """Run a precision schedule: stages = [(precision, max_iter, tol_E, stop_on_rise), ...]."""

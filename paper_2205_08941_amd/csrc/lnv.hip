@@ -50,6 +50,44 @@ double initial_scale(double nb, double ne, double t2, double t3)
                   [&](double c) { return 2 * (6 * c * t2 - 6 * c * c * t3); }, c0);
 }
 
+// Row sums of the force terms: one workgroup per atom I, out[3 I + c] =
+// 4 sum over the off-diagonal blocks s of row I of <K_s, dH^c_s> + <Wt_s, dS^c_s>
+// (elementwise), in a fixed order (strided partial sums, then a fixed tree).
+constexpr int kForceThreads = 256;
+__global__ __launch_bounds__(kForceThreads) void k_row_forces(int b, const int *__restrict__ rowptr,
+                                                              const int *__restrict__ cols,
+                                                              const double *__restrict__ K,
+                                                              const double *__restrict__ Wt,
+                                                              const double *__restrict__ dH0,
+                                                              const double *__restrict__ dH1,
+                                                              const double *__restrict__ dH2,
+                                                              const double *__restrict__ dS0,
+                                                              const double *__restrict__ dS1,
+                                                              const double *__restrict__ dS2, double *__restrict__ out)
+{
+    __shared__ double red[3][kForceThreads];
+    const int I = blockIdx.x, bb = b * b;
+    const int s0 = rowptr[I], s1 = rowptr[I + 1];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t e = (int64_t)s0 * bb + threadIdx.x; e < (int64_t)s1 * bb; e += kForceThreads) {
+        if (cols[e / bb] == I) continue;   // a block of the atom with itself does not move
+        const double k = K[e], w = Wt[e];
+        a0 += k * dH0[e] + w * dS0[e];
+        a1 += k * dH1[e] + w * dS1[e];
+        a2 += k * dH2[e] + w * dS2[e];
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    red[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int w = kForceThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[3 * I + threadIdx.x] = 4.0 * red[threadIdx.x][0];
+}
+
 }  // namespace
 }  // namespace bsm
 
@@ -138,6 +176,24 @@ struct lnv_state_s {
         trace_products(c, 4, X.p, a, X.p, b, tr);
         E = 2.0 * (3.0 * tr[0] - 2.0 * tr[1]);
         N = 2.0 * (3.0 * tr[2] - 2.0 * tr[3]);
+    }
+
+    // G_E = sym(6 (HX + (HX)^T) - 4 (HW + (HW)^T) - 4 S U), G_N = sym(12 (S X - S W)) on P_L
+    // from X, W, U of the current L
+    void gradients()
+    {
+        const int64_t nl = nelems(PL);
+        mul(1.0, PH, H, X.p, X.d(), 0.0, PL, t1.d());          // HX
+        add_transpose(c, PL, 6.0, t1.d(), 0.0, GE.d());        // 6 (HX + HX^T)
+        mul(1.0, PH, H, W.p, W.d(), 0.0, PL, t1.d());          // HW
+        add_transpose(c, PL, -4.0, t1.d(), 1.0, GE.d());       // - 4 (HW + HW^T)
+        mul(1.0, PS, S, U.p, U.d(), 0.0, PL, t1.d());          // SU
+        axpby(c, nl, -4.0, t1.d(), 1.0, GE.d());               // - 4 SU
+        symmetrize(c, PL, GE.d());
+        mul(1.0, PS, S, X.p, X.d(), 0.0, PL, t1.d());          // SX
+        mul(1.0, PS, S, W.p, W.d(), 0.0, PL, t2.d());          // SW
+        axpbypcz(c, nl, 12.0, t1.d(), -12.0, t2.d(), 0.0, GN.d());
+        symmetrize(c, PL, GN.d());
     }
 
     double dot1(const Mat &A, const Mat &B)
@@ -303,18 +359,8 @@ int lnv_state_s::step(lnv_result *res)
         }
 
         // ---- gradients on P_L
-        Mat &GE = st->GE, &GN = st->GN, &t1 = st->t1, &t2 = st->t2;
-        st->mul(1.0, st->PH, st->H, X.p, X.d(), 0.0, PL, t1.d());          // HX
-        add_transpose(c, PL, 6.0, t1.d(), 0.0, GE.d());                    // 6 (HX + HX^T)
-        st->mul(1.0, st->PH, st->H, W.p, W.d(), 0.0, PL, t1.d());          // HW
-        add_transpose(c, PL, -4.0, t1.d(), 1.0, GE.d());                   // - 4 (HW + HW^T)
-        st->mul(1.0, st->PS, st->S, U.p, U.d(), 0.0, PL, t1.d());          // SU
-        axpby(c, nl, -4.0, t1.d(), 1.0, GE.d());                           // - 4 SU
-        symmetrize(c, PL, GE.d());
-        st->mul(1.0, st->PS, st->S, X.p, X.d(), 0.0, PL, t1.d());          // SX
-        st->mul(1.0, st->PS, st->S, W.p, W.d(), 0.0, PL, t2.d());          // SW
-        axpbypcz(c, nl, 12.0, t1.d(), -12.0, t2.d(), 0.0, GN.d());
-        symmetrize(c, PL, GN.d());
+        Mat &GE = st->GE, &GN = st->GN;
+        st->gradients();
 
         // ---- preconditioned gradients, chemical potential, direction
         Mat &PE = st->PE, &PN = st->PN, &g = st->g, &Mg = st->Mg, &D = st->D;
@@ -439,6 +485,81 @@ extern "C" int lnv_idempotency_error(lnv_state *st, double *e_idem)
         st->prec = saved;
         *e_idem = std::sqrt(d[0]) / std::sqrt(d[1]);
         if (!std::isfinite(*e_idem)) return fail(BSM_ENONFINITE, "idempotency error is not finite");
+        return BSM_OK;
+    } catch (const Error &e) {
+        return fail(e.code, e.msg);
+    } catch (...) {
+        return fail(BSM_EINVAL, "unknown error");
+    }
+}
+
+extern "C" int lnv_forces(lnv_state *st, const bsm_matrix *dS, const bsm_matrix *dH, double *forces, double *mu_out)
+{
+    try {
+        BSM_REQUIRE(st && dS && dH && forces, BSM_EINVAL, "NULL argument");
+        Context *c = st->c;
+        const bsm_pattern_s *PS = st->PS, *PH = st->PH, *PL = st->PL;
+        BSM_REQUIRE(PS->cutoff == PH->cutoff && PS->nnzb == PH->nnzb, BSM_EPATTERN,
+                    "forces need S and H on the same pattern");
+        for (int k = 0; k < 3; ++k) {
+            check_matrix(&dS[k], "dS");
+            check_matrix(&dH[k], "dH");
+            BSM_REQUIRE(dS[k].pattern == PS && dH[k].pattern == PH, BSM_EPATTERN,
+                        "derivative blocks must be on the state's S and H patterns");
+        }
+        struct PrecGuard {   // FP64 products for the forces; the state's precision restored on every exit
+            lnv_state_s *s;
+            int p;
+            ~PrecGuard() { s->prec = p; }
+        } guard{st, st->prec};
+        st->prec = BSM_F64;
+        const int64_t ns = nelems(PS);
+        Mat &X = st->X, &Y = st->Y, &W = st->W, &U = st->U;
+        // chemical potential at the current L (canonical definition), as a step computes it
+        st->mul(1.0, PL, st->L, PS, st->S, 0.0, X.p, X.d());
+        st->mul(1.0, PL, st->L, PH, st->H, 0.0, Y.p, Y.d());
+        st->mul(X, X, W);
+        st->mul(Y, X, U);
+        st->gradients();
+        st->precondition(st->GE, st->PE);
+        st->precondition(st->GN, st->PN);
+        double gp[2];
+        {
+            const double *a[2] = {st->GN.d(), st->GN.d()}, *b[2] = {st->PN.d(), st->PE.d()};
+            dots(c, 2, PL, a, b, gp);
+        }
+        const double mu = (st->prm.mode == LNV_CANONICAL && gp[0] > 0.0) ? gp[1] / gp[0] : st->mu;
+        BSM_REQUIRE(std::isfinite(mu), BSM_ENONFINITE, "chemical potential is not finite");
+        // K = 3 LSL - 2 LSLSL on P_S (exact: W L reaches r_L beyond P(r_L + r_S))
+        Mat K(c, PS), K2(c, PS), Hp(c, PS), XM(c, PS), Wt(c, PS);
+        st->mul(1.0, X.p, X.d(), PL, st->L, 0.0, PS, K.d());
+        st->mul(1.0, W.p, W.d(), PL, st->L, 0.0, PS, K2.d());
+        axpby(c, ns, -2.0, K2.d(), 3.0, K.d());
+        // H' = H - mu S; M = (L H') L on P(r_L + r_S + r_S), exact where X M reads it
+        axpby(c, ns, 1.0, st->H, 0.0, Hp.d());
+        axpby(c, ns, -mu, st->S, 1.0, Hp.d());
+        Mat &LH = st->XD;   // P_X scratch
+        st->mul(1.0, PL, st->L, PS, Hp.d(), 0.0, LH.p, LH.d());
+        const bsm_pattern_s *PM = derived_pattern_cached(PL, st->PX->cutoff + PS->cutoff);
+        Mat M(c, PM);
+        st->mul(1.0, LH.p, LH.d(), PL, st->L, 0.0, PM, M.d());
+        st->mul(1.0, X.p, X.d(), PM, M.d(), 0.0, PS, XM.d());
+        // Wt = Q - mu K with Q = 3 mask_S(M) - 2 (X M + (X M)^T)
+        mask_copy(c, PM, M.d(), PS, Wt.d());
+        add_transpose(c, PS, -2.0, XM.d(), 3.0, Wt.d());
+        axpby(c, ns, -mu, K.d(), 1.0, Wt.d());
+        DevBuf out(c, sizeof(double) * 3 * (size_t)PS->natoms);
+        k_row_forces<<<PS->natoms, kForceThreads, 0, c->stream>>>(
+            PS->b, PS->rowptr.as<int>(), PS->cols.as<int>(), K.d(), Wt.d(), (const double *)dH[0].blocks,
+            (const double *)dH[1].blocks, (const double *)dH[2].blocks, (const double *)dS[0].blocks,
+            (const double *)dS[1].blocks, (const double *)dS[2].blocks, out.as<double>());
+        BSM_HIP_TRY(hipGetLastError());
+        BSM_HIP_TRY(hipMemcpyAsync(forces, out.ptr, sizeof(double) * 3 * PS->natoms, hipMemcpyDeviceToHost,
+                                   c->stream));
+        BSM_HIP_TRY(hipStreamSynchronize(c->stream));
+        if (mu_out) *mu_out = mu;
+        for (int64_t e = 0; e < 3 * (int64_t)PS->natoms; ++e)
+            if (!std::isfinite(forces[e])) return fail(BSM_ENONFINITE, "forces are not finite");
         return BSM_OK;
     } catch (const Error &e) {
         return fail(e.code, e.msg);
