@@ -40,13 +40,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="si4096_b9",
-                    choices=["si4096_b9", "si64_b4", "batch64", "si4096_b9_mixed", "guess", "invsqrt"],
+                    choices=["si4096_b9", "si64_b4", "batch64", "si4096_b9_mixed", "guess", "invsqrt", "forces"],
                     help="batch64: 64 uneven systems (512-4096 atoms, b = 4 and 9), the 16 A x 16 A -> 16 A "
                          "product of each, per-product launches against one tuned persistent launch; "
                          "si4096_b9_mixed: the solve with BF16 then FP32 products and 3 FP64 steps against "
                          "the FP64 solve; guess: networks trained on 512-atom displaced frames, a 4096-atom "
                          "displaced frame solved from the learned and from the plain starts; invsqrt: "
-                         "truncated S^-1/2 and S^1/2 of the 4096-atom overlap (coupled Newton-Schulz)")
+                         "truncated S^-1/2 and S^1/2 of the 4096-atom overlap (coupled Newton-Schulz); forces: "
+                         "forces of a converged 4096-atom displaced frame")
     ap.add_argument("--guess-train", type=int, default=12, help="training frames of the guess workload")
     ap.add_argument("--guess-cells", type=int, default=8, help="cells per side of the guess test frame")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -303,6 +304,93 @@ def invsqrt_mode(args):
     print(json.dumps(res), flush=True)
 
 
+def forces_mode(args):
+    """Forces of a converged 4096-atom, b = 9 displaced frame (geometry-smooth S and H):
+    one converged solve, then lnv_forces timed."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    t = time.perf_counter()
+    s = synth.make_system("si4096_b9_frame", 8, 9, synth.BIG_CUTOFFS, 10000, displacement_sigma=0.05,
+                          smooth=True, derivatives=True)
+    log(f"[forces] frame and derivative blocks generated in {time.perf_counter() - t:.1f} s")
+    ctx = bsm.Context(0)
+    pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
+    P6 = bsm.Pattern(ctx, pos, s.box, s.cutoffs["S"], s.b)
+    PZ = bsm.Pattern(ctx, pos, s.box, s.cutoffs["Z"], s.b)
+    PL = bsm.Pattern(ctx, pos, s.box, s.cutoffs["L"], s.b)
+
+    def filled(bl):
+        m = bsm.Matrix(P6)
+        bsm.fill_blocks(m, bl.rows, bl.cols, bl.blocks)
+        return m
+    S, H = filled(s.S), filled(s.H)
+    dS, dH = [filled(d) for d in s.dS], [filled(d) for d in s.dH]
+    Z, L = bsm.Matrix(PZ), bsm.Matrix(PL)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    hr = bsm.hotelling_inverse(S, Z, max_iter=100, tol=1e-12)
+    lnv = bsm.LNV(S, H, Z, L, s.n_electrons, tol_E=args.tol_e)
+    r = lnv.solve([(bsm.F64, args.max_lnv, args.tol_e, False)])
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t
+    for _ in range(args.warmup):
+        lnv.forces(dS, dH)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        F, mu = lnv.forces(dS, dH)
+    dt = (time.perf_counter() - t) / args.steps
+    stats = ctx.product_stats()
+    ctx.set_profiling(False)
+    flops = sum(st["flops"] for st in stats) / args.steps
+    top = max(stats, key=lambda st: st["ms"])
+    top_ms = top["ms"] / top["launches"]
+    top_tf = top["flops"] / top["launches"] / (top_ms * 1e-3) / 1e12
+    log(f"[forces] solve {t_solve:.2f} s ({hr.iterations} Hotelling, {r['iterations']} LNV), forces {dt:.3f} s, "
+        f"max |F| {np.abs(F).max():.4f} Ha/A, |sum F| {np.abs(F.sum(0)).max():.1e}")
+    res = {"metric": "s per force evaluation at the converged density matrix, 4096-atom 9-orb frame",
+           "value": round(dt, 4), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "4096-atom b = 9 displaced frame (sigma 0.05 A, geometry-smooth S and H), "
+                                  "converged LNV, then F = -dOmega/dR", "natoms": s.natoms, "orbitals_per_atom": s.b},
+           "solve_s": round(t_solve, 3), "lnv_iterations": r["iterations"], "mu": mu,
+           "max_abs_force": float(np.abs(F).max()), "abs_sum_force": float(np.abs(F.sum(0)).max()),
+           "product_gflops": round(flops / dt / 1e9, 1),
+           "roofline": {"bound": "alu", "kernel": f"{kernel_name(top)}: P{top['cutoffs'][0]:g} x "
+                                                  f"P{top['cutoffs'][1]:g} -> P{top['cutoffs'][2]:g}",
+                        "achieved": round(top_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(top_tf / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                        "avg_launch_ms": round(top_ms, 3), "launches": top["launches"]}}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = forces_cpu_baseline(s, L, Z, mu)
+    print(json.dumps(res), flush=True)
+
+
+def forces_cpu_baseline(s, L, Z, mu):
+    """The oracle's force assembly on the same frame, at the GPU-converged L and mu (its own
+    chemical-potential step, which needs two more 2 TFLOP products, skipped)."""
+    import oracle as O
+    P6 = O.create_pattern(s.positions, s.box, s.cutoffs["S"])
+    So = O.from_blocks(P6, s.b, s.S.rows, s.S.cols, s.S.blocks)
+    Ho = O.from_blocks(P6, s.b, s.H.rows, s.H.cols, s.H.blocks)
+    Zo = O.Matrix(O.create_pattern(s.positions, s.box, s.cutoffs["Z"]), s.b, Z.blocks.cpu().numpy())
+    PLo = O.create_pattern(s.positions, s.box, s.cutoffs["L"])
+    st = O.lnv_init(So, Ho, Zo, PLo, s.n_electrons, L0=O.Matrix(PLo, s.b, L.blocks.cpu().numpy()))
+    dS = [O.from_blocks(P6, s.b, d.rows, d.cols, d.blocks) for d in s.dS]
+    dH = [O.from_blocks(P6, s.b, d.rows, d.cols, d.blocks) for d in s.dH]
+    t = time.perf_counter()
+    O.lnv_forces(st, dS, dH, mu=mu)
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    return {"value": round(dt, 2), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"the oracle's force assembly (K, Q, row sums) on the same {s.natoms}-atom frame at the "
+                      f"GPU-converged L and mu, {dt:.1f} s"}
+
+
 def invsqrt_cpu_baseline(s, updates):
     """The oracle on the same workload (its P(2 r_Z) pattern build included), timed for
     its start and for 2 updates, and extrapolated linearly to the GPU run's number of
@@ -451,6 +539,9 @@ def main():
         return
     if args.workload == "invsqrt":
         invsqrt_mode(args)
+        return
+    if args.workload == "forces":
+        forces_mode(args)
         return
     s = synth.si4096_b9() if args.workload == "si4096_b9" else synth.si64_b4()
     cut = s.cutoffs

@@ -724,7 +724,7 @@ def lnv_chemical_potential(st: LNVState) -> float:
     return dot(GN, PE) / dot(GN, PN)
 
 
-def lnv_forces(st: LNVState, dS: List[Matrix], dH: List[Matrix]) -> np.ndarray:
+def lnv_forces(st: LNVState, dS: List[Matrix], dH: List[Matrix], mu: Optional[float] = None) -> np.ndarray:
     """Forces F_I = -d Omega / d R_I at a converged L, Omega = E - mu (N - N_e).
 
     The paper lists forces with the solver's next capabilities; this is the
@@ -738,13 +738,15 @@ def lnv_forces(st: LNVState, dS: List[Matrix], dH: List[Matrix]) -> np.ndarray:
     row:  F_I^c = 4 sum_{j != I} <K_Ij, dH^c_Ij> + <(Q - mu K)_Ij, dS^c_Ij>  (elementwise).
     Needs r_S == r_H.  Q is exact on P_S: L H' on P_X = P(r_L + r_S), M = L H' L
     on P(r_X + r_S) (all that X M reads for outputs on P_S), X M with X = L S
-    masked to P_S.
+    masked to P_S.  mu: the chemical potential to use (default: from the current
+    gradients, lnv_chemical_potential).
     """
     S, H, L = st.S, st.H, st.L
     PS = S.pattern
     assert abs(PS.cutoff - H.pattern.cutoff) < 1e-12, "forces need the S and H patterns equal"
     b = S.b
-    mu = lnv_chemical_potential(st)
+    if mu is None:
+        mu = lnv_chemical_potential(st)
     K = density_matrix(st, PS)
     Hp = Matrix(PS, b, H.blocks - mu * S.blocks)
     X = product(L, S, st.PX)
