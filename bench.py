@@ -40,14 +40,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="si4096_b9",
-                    choices=["si4096_b9", "si64_b4", "batch64", "si4096_b9_mixed", "guess", "invsqrt", "forces"],
+                    choices=["si4096_b9", "si64_b4", "batch64", "si4096_b9_mixed", "guess", "invsqrt", "forces",
+                             "contract"],
                     help="batch64: 64 uneven systems (512-4096 atoms, b = 4 and 9), the 16 A x 16 A -> 16 A "
                          "product of each, per-product launches against one tuned persistent launch; "
                          "si4096_b9_mixed: the solve with BF16 then FP32 products and 3 FP64 steps against "
                          "the FP64 solve; guess: networks trained on 512-atom displaced frames, a 4096-atom "
                          "displaced frame solved from the learned and from the plain starts; invsqrt: "
                          "truncated S^-1/2 and S^1/2 of the 4096-atom overlap (coupled Newton-Schulz); forces: "
-                         "forces of a converged 4096-atom displaced frame")
+                         "forces of a converged 4096-atom displaced frame; contract: the 4096-atom system "
+                         "contracted to 4 on-site support functions per atom and solved, against the 9-orbital solve")
     ap.add_argument("--guess-train", type=int, default=12, help="training frames of the guess workload")
     ap.add_argument("--guess-cells", type=int, default=8, help="cells per side of the guess test frame")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -370,6 +372,107 @@ def forces_mode(args):
     print(json.dumps(res), flush=True)
 
 
+def onsite_coefficients(s, bc):
+    """The bc lowest eigenvectors of every on-site H block (input preparation on the host)."""
+    import numpy as np
+    on = s.H.rows == s.H.cols
+    order = np.argsort(s.H.rows[on])
+    return np.stack([np.linalg.eigh(blk)[1][:, :bc] for blk in s.H.blocks[on][order]])
+
+
+def contract_mode(args):
+    """The 4096-atom, b = 9 system contracted to 4 on-site support functions per atom
+    (bsm_contract) and solved at b = 4, against the 9-orbital solve in the same run."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    s = synth.si4096_b9()
+    bc = 4
+    coef = onsite_coefficients(s, bc)
+    ctx = bsm.Context(0)
+    pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
+    cut = s.cutoffs
+    P9 = bsm.Pattern(ctx, pos, s.box, cut["S"], 9)
+    S9, H9 = bsm.Matrix(P9), bsm.Matrix(P9)
+    bsm.fill_blocks(S9, s.S.rows, s.S.cols, s.S.blocks)
+    bsm.fill_blocks(H9, s.H.rows, s.H.cols, s.H.blocks)
+    ct = torch.tensor(coef, dtype=torch.float64, device=ctx.device).contiguous()
+
+    def solve(b, contracted):
+        P6 = P9 if b == 9 else bsm.Pattern(ctx, pos, s.box, cut["S"], b)
+        Z = bsm.Matrix(bsm.Pattern(ctx, pos, s.box, cut["Z"], b))
+        L = bsm.Matrix(bsm.Pattern(ctx, pos, s.box, cut["L"], b))
+        out = None
+        for rep in range(args.warmup + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if contracted:
+                S, H = bsm.Matrix(P6), bsm.Matrix(P6)
+                bsm.contract(S9, ct, S)
+                bsm.contract(H9, ct, H)
+            else:
+                S, H = S9, H9
+            if rep == args.warmup:
+                ctx.set_profiling(True)
+            hr = bsm.hotelling_inverse(S, Z, max_iter=100, tol=1e-12)
+            lnv = bsm.LNV(S, H, Z, L, s.n_electrons, tol_E=args.tol_e)
+            r = lnv.solve([(bsm.F64, args.max_lnv, args.tol_e, False)])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            out = dict(seconds=round(dt, 3), E=r["E"], lnv=r["iterations"][0], hotelling=hr.iterations,
+                       converged=r["converged"])
+        stats = ctx.product_stats()
+        ctx.set_profiling(False)
+        return out, stats
+
+    full, _ = solve(9, False)
+    con, stats = solve(bc, True)
+    dE = (con["E"] - full["E"]) / s.natoms
+    top = max(stats, key=lambda st: st["ms"])
+    top_ms = top["ms"] / top["launches"]
+    top_tf = top["flops"] / top["launches"] / (top_ms * 1e-3) / 1e12
+    log(f"[contract] 9 orbitals: {full['seconds']:.2f} s, E {full['E']:.6f}; {bc} support functions: "
+        f"{con['seconds']:.2f} s, E {con['E']:.6f}, dE/N {dE:.3e} Ha")
+    res = {"metric": "s per converged LNV solve, 4096-atom system contracted to 4 on-site support functions",
+           "value": con["seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+           "ms_per_step": con["seconds"] * 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "si4096_b9 contracted to 4 support functions per atom (lowest on-site H "
+                                  "eigenvectors), contraction + Hotelling + LNV at b = 4",
+                      "natoms": s.natoms, "orbitals_per_atom": 9, "support_functions_per_atom": bc},
+           "contracted": con, "full_9_orbitals": full, "dE_per_atom_Ha": dE,
+           "speedup_vs_9_orbitals": round(full["seconds"] / con["seconds"], 3),
+           "roofline": {"bound": "alu", "kernel": f"{kernel_name(top)}: P{top['cutoffs'][0]:g} x "
+                                                  f"P{top['cutoffs'][1]:g} -> P{top['cutoffs'][2]:g}",
+                        "achieved": round(top_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(top_tf / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                        "avg_launch_ms": round(top_ms, 3), "launches": top["launches"]}}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = contract_cpu_baseline(s, coef, con["lnv"])
+    print(json.dumps(res), flush=True)
+
+
+def contract_cpu_baseline(s, coef, lnv_iterations):
+    """The oracle on the same contracted workload: contraction, Hotelling and the first
+    LNV step timed, the step extrapolated linearly to the GPU run's LNV iteration count."""
+    import oracle as O
+    P6 = O.create_pattern(s.positions, s.box, s.cutoffs["S"])
+    t = time.perf_counter()
+    S = O.contract(O.from_blocks(P6, s.b, s.S.rows, s.S.cols, s.S.blocks), coef)
+    H = O.contract(O.from_blocks(P6, s.b, s.H.rows, s.H.cols, s.H.blocks), coef)
+    Z = O.hotelling_inverse(S, O.create_pattern(s.positions, s.box, s.cutoffs["Z"]), max_iter=100).Z
+    st = O.lnv_init(S, H, Z, O.create_pattern(s.positions, s.box, s.cutoffs["L"]), s.n_electrons)
+    t_setup = time.perf_counter() - t
+    t = time.perf_counter()
+    O.lnv_step(st)
+    t_step = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    return {"value": round(t_setup + lnv_iterations * t_step, 2), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"the same contracted {s.natoms}-atom workload: contraction + Hotelling + L0 {t_setup:.1f} s "
+                      f"and one LNV step {t_step:.1f} s timed, extrapolated to {lnv_iterations} steps"}
+
+
 def forces_cpu_baseline(s, L, Z, mu):
     """The oracle's force assembly on the same frame, at the GPU-converged L and mu (its own
     chemical-potential step, which needs two more 2 TFLOP products, skipped)."""
@@ -542,6 +645,9 @@ def main():
         return
     if args.workload == "forces":
         forces_mode(args)
+        return
+    if args.workload == "contract":
+        contract_mode(args)
         return
     s = synth.si4096_b9() if args.workload == "si4096_b9" else synth.si64_b4()
     cut = s.cutoffs

@@ -211,6 +211,14 @@ int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const 
  * extension built on the method, not in the paper). */
 int bsm_multiply_truncate_prec(bsm_ctx ctx, int precision, double alpha, const bsm_matrix *A,
                                const bsm_matrix *B, double beta, const bsm_matrix *C);
+/* Contraction to support functions (the on-site equivalent of multi-site
+ * support functions, Development Priorities): every block of M (b x b) becomes
+ * M'_ij = C_i^T M_ij C_j (bc x bc) in out, whose pattern has the same atoms and
+ * cutoff with bc = out's orbitals per atom (bc <= b).  coef: device,
+ * natoms x b x bc doubles, C_i[a][alpha] at coef[(i b + a) bc + alpha], caller-owned.
+ * Asynchronous on the context stream.  Errors: BSM_EPATTERN (patterns differ),
+ * BSM_EINVAL (bc > b, aliasing). */
+int bsm_contract(bsm_ctx ctx, const bsm_matrix *M, const double *coef, const bsm_matrix *out);
 /* ---- many products in one persistent launch (an extension: uneven systems) 
  * A batch of independent products C_p <- alpha_p mask(A_p B_p) + beta_p C_p,
  * b = 4 or 9 (e.g. one per system of a batch of uneven systems), runs as one

@@ -18,8 +18,8 @@ What it computes, and where it comes from:
   inversion for symmetric (Loewdin) orthogonalisation;
 * forces -dOmega/dR at the converged density matrix (Hellmann-Feynman and
   energy-density-matrix terms), from derivative blocks of S and H;
-* contraction of S and H to a few support functions per atom (single-site form
-  of the multi-site contraction the paper describes for CONQUEST);
+* contraction of S and H to a few support functions per atom (the on-site
+  equivalent of multi-site support functions, Development Priorities);
 * LNV density-matrix minimisation, K = 3LSL - 2LSLSL -- the paper's linear
   scaling O(N) ground-state solver (Background; Meeting the Exascale
   Challenges), in the non-orthogonal form of Li, Nunes and Vanderbilt (1993)
@@ -774,9 +774,9 @@ def lnv_forces(st: LNVState, dS: List[Matrix], dH: List[Matrix], mu: Optional[fl
 def contract(M: Matrix, coef: np.ndarray) -> Matrix:
     """Blocks of M in a basis of bc support functions per atom, each a combination of
     the atom's own b orbitals with coefficients coef[i] (b x bc):  M'_ij = C_i^T M_ij C_j
-    on the same pattern (single-site support functions, the on-site case of the
-    multi-site contraction the paper names as CONQUEST's route to fewer functions
-    per atom)."""
+    on the same pattern: single-site support functions, the on-site equivalent of
+    multi-site support functions that the paper lists among its development
+    priorities for PAO basis sets (Development Priorities)."""
     coef = np.asarray(coef, np.float64)
     P = M.pattern
     rows, cols = P.rows(), P.cols

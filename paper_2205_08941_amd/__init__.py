@@ -6,7 +6,7 @@ and fails if it has not been built; there is no CPU fallback."""
 from .bsm import (BSMError, Context, Pattern, Matrix, LNV, Batch, ORDER_BY_PRODUCT, ORDER_HEAVY_FIRST,
                   ORDER_INTERLEAVE, LNVResult, HotellingResult, fill_blocks,
                   multiply_truncate, multiply_truncate_prec, product_flops, trace_product, dot, axpby, symmetrize, mask_copy,
-                  set_identity, hotelling_inverse, inverse_sqrt, load_library, LIB_PATH, EXPORTS,
+                  set_identity, hotelling_inverse, inverse_sqrt, contract, load_library, LIB_PATH, EXPORTS,
                   OK, EINVAL, ENOMEM, EPATTERN, EHIP, ENONFINITE, EDIVERGED, ENOTCONV, ERUNAWAY,
                   CANONICAL, GRAND, F64, F32, BF16,
                   MLP, pair_descriptors, mlp_targets, mlp_param_count, DESC_DIM, MLP_WIDTH,

@@ -157,6 +157,7 @@ EXPORTS = {
     "bsm_batch_destroy": (c_int, [c_void_p]),
     "hotelling_inverse": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                   ctypes.POINTER(_HotParams), ctypes.POINTER(_HotResult)]),
+    "bsm_contract": (c_int, [c_void_p, ctypes.POINTER(_Matrix), c_void_p, ctypes.POINTER(_Matrix)]),
     "bsm_inverse_sqrt": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                  ctypes.POINTER(_Matrix), ctypes.POINTER(_HotParams), ctypes.POINTER(_HotResult)]),
     "lnv_state_create": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
@@ -470,6 +471,13 @@ def hotelling_inverse(S: Matrix, Z: Matrix, max_iter: int = 100, tol: float = 1e
         _check(code)
     return HotellingResult(res.status, res.iterations, res.alpha, list(buf[: min(res.n_residuals, cap)]),
                            res.product_flops, res.start)
+
+
+def contract(M: Matrix, coef: torch.Tensor, out: Matrix) -> None:
+    """out <- blocks C_i^T M_ij C_j; coef a device float64 tensor (natoms, b, bc), bc = out's b."""
+    assert coef.dtype == torch.float64 and coef.is_cuda and coef.is_contiguous()
+    assert tuple(coef.shape) == (M.pattern.natoms, M.pattern.b, out.pattern.b)
+    _check(_lib.bsm_contract(out.pattern.ctx.handle, M.c, c_void_p(coef.data_ptr()), out.c))
 
 
 def inverse_sqrt(S: Matrix, Z: Matrix, Y: Optional[Matrix] = None, max_iter: int = 100, tol: float = 1e-12,
