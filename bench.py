@@ -64,6 +64,8 @@ def parse():
                     help="operand precision of the --mode product launches")
     ap.add_argument("--rows", type=int, default=0,
                     help="rows per tile for --mode product (0: the library default)")
+    ap.add_argument("--column-order", type=int, default=-1, choices=[-1, 0, 1],
+                    help="tile column order for --mode product (-1: the library default)")
     ap.add_argument("--mode", default="solve", choices=["solve", "product"],
                     help="product: only the dominant 16 A x 16 A -> 16 A product, --steps launches, plus a "
                          "2 GiB device copy (for hardware-counter runs and their byte calibration)")
@@ -81,6 +83,8 @@ def product_mode(args):
     ctx = bsm.Context(0)
     ctx.set_product_variant(args.variant)
     ctx.set_rows_per_wave(args.rows)
+    if args.column_order >= 0:
+        ctx.set_column_order(args.column_order)
     pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
     P = bsm.Pattern(ctx, pos, s.box, rx, b)
     g = torch.Generator(device=ctx.device)
@@ -101,7 +105,8 @@ def product_mode(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     ms = st["ms"] / st["launches"]
-    print(json.dumps({"mode": "product", "precision": args.prec, "kernel": kernel_name(st),
+    print(json.dumps({"mode": "product", "precision": args.prec, "column_order": args.column_order,
+                      "kernel": kernel_name(st),
                       "sources_sha256_16": kernel_sources_sha(),
                       "flops_per_launch": flops, "avg_ms": ms,
                       "tflops": flops / (ms * 1e-3) / 1e12, "blocks": P.nnzb,

@@ -145,6 +145,17 @@ int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant);
  * 1 <= span <= 4096 (default 4).  Clears cached plans. */
 int bsm_ctx_set_group_span(bsm_ctx ctx, int span);
 
+/* Columns of the tiles of product plans built from now on.  Each group of
+ * rows-per-tile consecutive rows covers the union of its rows of P_C in tiles of
+ * 64 / b columns: order 0 takes the union in ascending column order; order 1
+ * (default) first groups the columns by the set of the group's rows that hold an
+ * output in them, so that within a tile every row multiplies only where it has
+ * outputs (fewer idle lanes, fewer copied A blocks, somewhat more entries).  For
+ * finite operands FP64 and FP32 products are equal under both orders (each
+ * element sums the same nonzero terms in ascending k); BF16 matrix-core products
+ * pair entries differently and may differ in rounding.  order must be 0 or 1.  Clears cached plans (destroy batches first). */
+int bsm_ctx_set_column_order(bsm_ctx ctx, int order);
+
 /* enable != 0 clears the statistics and starts recording; 0 stops. */
 int bsm_ctx_set_profiling(bsm_ctx ctx, int enable);
 /* Synchronises the stream, then writes up to `max` classes (most time first)

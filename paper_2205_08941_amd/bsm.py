@@ -128,6 +128,7 @@ EXPORTS = {
     "bsm_ctx_set_rows_per_wave": (c_int, [c_void_p, c_int]),
     "bsm_ctx_set_product_variant": (c_int, [c_void_p, c_int]),
     "bsm_ctx_set_group_span": (c_int, [c_void_p, c_int]),
+    "bsm_ctx_set_column_order": (c_int, [c_void_p, c_int]),
     "bsm_ctx_product_stats": (c_int, [c_void_p, ctypes.POINTER(_ProductStat), c_int, ctypes.POINTER(c_int)]),
     "bsm_create_pattern": (c_int, [c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_double), c_double,
                                    ctypes.POINTER(c_void_p)]),
@@ -259,6 +260,11 @@ class Context:
     def set_group_span(self, span: int) -> None:
         """Row groups interleaved by column position in the product launch order."""
         _check(_lib.bsm_ctx_set_group_span(self.handle, int(span)))
+
+    def set_column_order(self, order: int) -> None:
+        """Tile columns of plans built from now on: 0 ascending, 1 grouped by the rows they
+        hold outputs for (default); same products either way.  Clears cached plans."""
+        _check(_lib.bsm_ctx_set_column_order(self.handle, int(order)))
 
     def product_stats(self) -> list:
         """Per (P_A, P_B, P_C) class: launches, algorithmic flops, event milliseconds."""

@@ -256,6 +256,19 @@ int bsm_ctx_set_group_span(bsm_ctx ctx, int span)
     BSM_API_END
 }
 
+int bsm_ctx_set_column_order(bsm_ctx ctx, int order)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
+    BSM_REQUIRE(order == 0 || order == 1, BSM_EINVAL, "column order must be 0 or 1");
+    BSM_HIP_TRY(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.retire_profile([](const Plan *) { return true; });
+    ctx->c.plans.clear();
+    ctx->c.column_order = order;
+    return BSM_OK;
+    BSM_API_END
+}
+
 int bsm_ctx_set_profiling(bsm_ctx ctx, int enable)
 {
     BSM_API_BEGIN

@@ -85,6 +85,7 @@ class Context {
     int rows_per_wave = 0;      // product plans: 0 = per-b default, else 2, 4 or 8
     int product_variant = -1;   // product kernel variant of plans built from now on (-1: per-b default)
     int group_span = 4;         // row groups interleaved in product launch order
+    int column_order = 1;       // tile columns: 0 ascending, 1 grouped by the rows they hold outputs for
     // derived patterns (same atoms, another cutoff), owned here, keyed by (source id, cutoff)
     std::map<std::pair<uint64_t, double>, bsm_pattern_s *> derived;
     std::map<std::tuple<uint64_t, uint64_t, uint64_t, int, int>, std::unique_ptr<Plan>> plans;   // (A, B, C, variant, rows)

@@ -195,9 +195,18 @@ __global__ void k_group_union(int n, int G, const int *__restrict__ rpC, const i
     ntile[g] = (cnt + jt - 1) / jt;
 }
 
-// One thread per row group: write the tile headers of its runs.
-__global__ void k_group_tiles(int n, int G, int jt, const int *__restrict__ rpC, const int *__restrict__ cC,
-                              const int64_t *__restrict__ toff, int *__restrict__ hdr, int *__restrict__ tcols)
+// One thread per row group: write the tile headers of its runs.  The group's
+// union of P_C columns is cut into runs of jt columns, in ascending column order
+// (order 0) or grouped by the set of the group's rows whose P_C row holds the
+// column (order 1: row sets in descending bit order, ascending columns inside a
+// set).  With order 1 a tile's columns share their output rows, so a row
+// multiplies in a tile only where it has outputs; the two orders give the same
+// products.  cbuf / mbuf: two ping-pong halves of 2 * ntiles * jt ints each
+// (column, row set), used by order 1 only.
+__global__ void k_group_tiles(int n, int G, int jt, int order, const int *__restrict__ rpC,
+                              const int *__restrict__ cC, const int64_t *__restrict__ toff, int64_t ntiles,
+                              int *__restrict__ hdr, int *__restrict__ tcols, int *__restrict__ cbuf,
+                              int *__restrict__ mbuf)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int ng = (n + G - 1) / G;
@@ -209,30 +218,81 @@ __global__ void k_group_tiles(int n, int G, int jt, const int *__restrict__ rpC,
         p[a] = rpC[i0 + a];
         pe[a] = rpC[i0 + a + 1];
     }
-    int64_t t = toff[g];
-    int q = 0;
-    int *h = nullptr;
+    const int64_t t0 = toff[g], cap = ntiles * jt;
+    auto open_tile = [&](int64_t t) {
+        int *h = hdr + t * hs;
+        for (int a = 0; a < G; ++a) h[a] = (a < gr) ? i0 + a : -1;
+        for (int x = 0; x < G * jt; ++x) h[G + x] = -1;
+        for (int x = 0; x < jt; ++x) tcols[t * jt + x] = -1;
+    };
+    if (order == 0) {
+        int64_t t = t0;
+        int q = 0;
+        while (true) {
+            int m = 0x7fffffff;
+            for (int a = 0; a < gr; ++a)
+                if (p[a] < pe[a]) m = min(m, cC[p[a]]);
+            if (m == 0x7fffffff) break;
+            if (q == 0) open_tile(t);
+            int *h = hdr + t * hs;
+            tcols[t * jt + q] = m;
+            for (int a = 0; a < gr; ++a)
+                if (p[a] < pe[a] && cC[p[a]] == m) {
+                    h[G + a * jt + q] = p[a];
+                    ++p[a];
+                }
+            if (++q == jt) {
+                q = 0;
+                ++t;
+            }
+        }
+        return;
+    }
+    // order 1: union with row sets, then a stable radix sort on the row-set bits
+    // (least significant first, rows present before rows absent at each bit)
+    int *c0 = cbuf + t0 * jt, *m0 = mbuf + t0 * jt, *c1 = c0 + cap, *m1 = m0 + cap;
+    int cnt = 0;
     while (true) {
         int m = 0x7fffffff;
         for (int a = 0; a < gr; ++a)
             if (p[a] < pe[a]) m = min(m, cC[p[a]]);
         if (m == 0x7fffffff) break;
-        if (q == 0) {
-            h = hdr + t * hs;
-            for (int a = 0; a < G; ++a) h[a] = (a < gr) ? i0 + a : -1;
-            for (int x = 0; x < G * jt; ++x) h[G + x] = -1;
-            for (int x = 0; x < jt; ++x) tcols[t * jt + x] = -1;
-        }
-        tcols[t * jt + q] = m;
+        int set = 0;
         for (int a = 0; a < gr; ++a)
             if (p[a] < pe[a] && cC[p[a]] == m) {
-                h[G + a * jt + q] = p[a];
+                set |= 1 << a;
                 ++p[a];
             }
-        if (++q == jt) {
-            q = 0;
-            ++t;
-        }
+        c0[cnt] = m;
+        m0[cnt] = set;
+        ++cnt;
+    }
+    for (int bit = 0; bit < gr; ++bit) {
+        int w = 0;
+        for (int x = 0; x < cnt; ++x)
+            if ((m0[x] >> bit) & 1) {
+                c1[w] = c0[x];
+                m1[w++] = m0[x];
+            }
+        for (int x = 0; x < cnt; ++x)
+            if (!((m0[x] >> bit) & 1)) {
+                c1[w] = c0[x];
+                m1[w++] = m0[x];
+            }
+        int *tc = c0, *tm = m0;
+        c0 = c1;
+        m0 = m1;
+        c1 = tc;
+        m1 = tm;
+    }
+    for (int x = 0; x < cnt; ++x) {
+        const int64_t t = t0 + x / jt;
+        const int q = x % jt;
+        if (q == 0) open_tile(t);
+        int *h = hdr + t * hs;
+        tcols[t * jt + q] = c0[x];
+        for (int a = 0; a < gr; ++a)
+            if ((m0[x] >> a) & 1) h[G + a * jt + q] = find_in_row(rpC, cC, i0 + a, c0[x]);
     }
 }
 
@@ -520,8 +580,15 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
     }
     plan->hdr = DevBuf(ctx, sizeof(int) * (size_t)std::max<int64_t>(1, nt * hs));
     DevBuf tcols(ctx, sizeof(int) * (size_t)std::max<int64_t>(1, nt * jt));
-    k_group_tiles<<<(ng + 127) / 128, 128, 0, st>>>(n, G, jt, PC->rowptr.as<int>(), PC->cols.as<int>(),
-                                                    toff.as<int64_t>(), plan->hdr.as<int>(), tcols.as<int>());
+    {
+        const int order = ctx->column_order;
+        const size_t sortn = order == 1 ? (size_t)std::max<int64_t>(1, 2 * nt * jt) : 1;
+        DevBuf cbuf(ctx, sizeof(int) * sortn), mbuf(ctx, sizeof(int) * sortn);
+        k_group_tiles<<<(ng + 127) / 128, 128, 0, st>>>(n, G, jt, order, PC->rowptr.as<int>(), PC->cols.as<int>(),
+                                                        toff.as<int64_t>(), nt, plan->hdr.as<int>(),
+                                                        tcols.as<int>(), cbuf.as<int>(), mbuf.as<int>());
+        BSM_HIP_TRY(hipStreamSynchronize(st));   // before the sort buffers are freed
+    }
     DevBuf nent(ctx, sizeof(int64_t) * (size_t)std::max<int64_t>(1, nt)), tri(ctx, sizeof(unsigned long long));
     plan->ebeg = DevBuf(ctx, sizeof(int64_t) * (size_t)(nt + 1));
     BSM_HIP_TRY(hipMemsetAsync(tri.ptr, 0, sizeof(unsigned long long), st));

@@ -194,6 +194,61 @@ def test_product_degenerate_cases(bsm, b, variant, rows):
     ctx.close()
 
 
+@pytest.mark.parametrize("variant,rows", [(4, 8), (4, 4), (3, 2), (1, 4), (2, 0), (0, 2)])
+@pytest.mark.parametrize("b", [4, 9])
+def test_product_column_orders_agree(bsm, b, variant, rows):
+    """Tiles over ascending columns (order 0) and over columns grouped by the rows
+    that hold outputs in them (order 1, the default) cover the same output blocks:
+    FP64 and FP32 products are equal element by element (the nonzero terms of each
+    element are summed in the same ascending k order), and both match the oracle;
+    BF16 on the matrix cores matches the oracle under both orders.  216 atoms: the 16-row workgroup tiles end half empty."""
+    s = SYSTEMS["si216_disp"]()
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
+    cases = [(6, 8, 14), (14, 8, 6), (8, 14, 8)]
+    data = [(synth.random_blocks(op[ra].nnz, b, 110 + n), synth.random_blocks(op[rb].nnz, b, 120 + n),
+             synth.random_blocks(op[rc].nnz, b, 130 + n)) for n, (ra, rb, rc) in enumerate(cases)]
+    out = {}
+    mfma = b == 9 and variant in (3, 4) and rows in (4, 8)   # BF16 on the matrix cores
+    precs = (bsm.F64, bsm.F32, bsm.BF16) if mfma else (bsm.F64, bsm.F32)
+    for order in (0, 1):
+        ctx = bsm.Context(0)
+        ctx.set_product_variant(variant)
+        ctx.set_rows_per_wave(rows)
+        ctx.set_column_order(order)
+        say(f"column order={order} variant={variant} rows={rows} b={b}")
+        gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
+        for n, (ra, rb, rc) in enumerate(cases):
+            a, bb, c0 = data[n]
+            for prec in precs:
+                C = gmat(bsm, gp[rc], c0)
+                bsm.multiply_truncate_prec(prec, 1.25, gmat(bsm, gp[ra], a), gmat(bsm, gp[rb], bb), 0.5, C)
+                out[order, n, prec] = host(C)
+        ctx.close()
+    if mfma:   # matrix cores: entries paired differently, so compared with the oracle only
+        for order in (0, 1):
+            for n, (ra, rb, rc) in enumerate(cases):
+                a, bb, c0 = data[n]
+                Co = O.Matrix(op[rc], b, c0.copy())
+                O.multiply_truncate_mixed(2, 1.25, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), 0.5, Co)
+                assert rel_err(out[order, n, bsm.BF16], Co.blocks) < 2e-6, (order, ra, rb, rc)
+    for n, (ra, rb, rc) in enumerate(cases):
+        a, bb, c0 = data[n]
+        for prec in (bsm.F64, bsm.F32):
+            assert np.array_equal(out[0, n, prec], out[1, n, prec]), (n, prec)
+            Co = O.Matrix(op[rc], b, c0.copy())
+            if prec == bsm.F64:
+                O.multiply_truncate(1.25, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), 0.5, Co)
+                assert rel_err(out[1, n, prec], Co.blocks) < 1e-12, (ra, rb, rc)
+            else:
+                O.multiply_truncate_mixed(1, 1.25, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), 0.5, Co)
+                assert rel_err(out[1, n, prec], Co.blocks) < 1e-14, (ra, rb, rc)
+
+
+def test_column_order_rejects_bad_value(bsm, ctx):
+    with pytest.raises(bsm.BSMError):
+        ctx.set_column_order(2)
+
+
 def test_product_beta_zero_ignores_nan_and_is_deterministic(bsm, ctx):
     s = SYSTEMS["si64"]()
     P6, P8 = (gpat(bsm, ctx, s.positions, s.box, r, 4) for r in (6.0, 8.0))
