@@ -133,7 +133,13 @@ int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
  * 2 (3, at 2 or 4 rows) or 1 (4, and 3 at 8 rows) entries ahead (b = 4 and 9,
  * rows 2, 4 or 8, else 0); 3 addresses the copies with 64-bit pointers, 4
  * through buffer resources when A and B each hold at most 0xfffff000 bytes
- * (else as 3); -1 = default (4 for b = 4 and 9, with 8 rows per tile, else 0).
+ * (else as 3); 5 = the rings of 4 with each tile of twice the columns shared by
+ * the two waves of a workgroup: one list of k per tile, a half entry per wave
+ * (A slots of the rows with outputs in that wave's columns, its B slots), a
+ * barrier per entry so that both waves copy the same A blocks together (the
+ * second copy is served from cache); rows 4 or 8 (2 gives 4); BF16 products at
+ * b = 9 use one-wave plans on the matrix cores; -1 = default (4 for b = 4 and 9,
+ * with 8 rows per tile, else 0).
  * Variants 1 to 4 multiply absent (k, j) blocks by zero instead of skipping
  * them, so a non-finite block of A can make other blocks of its output row
  * non-finite.  Clears cached plans (a bsm_batch made before keeps pointers to

@@ -61,15 +61,17 @@ struct Plan {
     double cutoffs[3] = {0, 0, 0};
     int natoms = 0, b = 0;
     int G = 0;                  // rows per wavefront tile
-    int variant = 0;            // 0: A through SGPRs, 1: A in VGPRs with DPP broadcast, 2: workgroup tiles
-    int jt = 0;                 // output block columns per wavefront tile (64 / b)
+    int variant = 0;            // 0: A through SGPRs, 1: A in VGPRs with DPP broadcast, 2: workgroup tiles,
+                                // 3, 4: LDS-DMA rings, 5: rings with tiles shared by two waves
+    int waves = 1;              // waves per tile (2 for variant 5)
+    int jt = 0;                 // output block columns per tile (waves * 64 / b)
     int64_t ntiles = 0;
     int64_t nentries = 0;
     int span = 1;               // row groups interleaved in the launch order
     DevBuf order;               // int [ntiles]: launch slot -> tile
     DevBuf hdr;                 // int [ntiles][G + G*jt]: rows, C slots
     DevBuf ebeg;                // int64 [ntiles + 1]: entry ranges
-    DevBuf ent;                 // int [nentries][G + jt]: A slots, B slots
+    DevBuf ent;                 // int [nentries][waves * G + jt]: per wave A slots, then its B slots
     double flops = 0.0;         // algorithmic: 2 b^3 per block triple
     int64_t triples = 0;
 };
@@ -163,7 +165,8 @@ bsm_pattern_s *derived_pattern(const bsm_pattern_s *p, double cutoff);
 const bsm_pattern_s *derived_pattern_cached(const bsm_pattern_s *p, double cutoff);
 void destroy_pattern(bsm_pattern_s *p);
 Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C);
-// A plan of a given kernel variant (0: SGPR, 1: DPP wave tiles, 2: workgroup tiles) and rows per tile.
+// A plan of a given kernel variant (0: SGPR, 1: DPP wave tiles, 2: workgroup tiles, 3 and 4: LDS-DMA
+// rings, 5: rings with tiles shared by two waves) and rows per tile.
 Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C,
                     int variant, int G);
 
@@ -172,7 +175,7 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
                         const double *A, const bsm_pattern_s *PB, const double *B, double beta,
                         const bsm_pattern_s *PC, double *C);
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
-                Plan *plan, int G);
+                Plan *plan, int G, int waves);
 // prec BSM_F64: the FP64 product; BSM_F32 / BSM_BF16: operands rounded to that
 // precision, FP32 accumulation, FP64 result.
 void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha, const bsm_pattern_s *PA,

@@ -85,18 +85,20 @@ __global__ __launch_bounds__(256) void k_product_wg(
 
 // One wave tile per one-wave workgroup, operands through a per-wave LDS ring
 // (BUF: copied through buffer resources of a_bytes and b_bytes).
-template <int B, int G, int D, class T = double, bool BUF = false>
-__global__ __launch_bounds__(64) void k_product_ring(
+template <int B, int G, int D, class T = double, bool BUF = false, int W = 1>
+__global__ __launch_bounds__(64 * W) void k_product_ring(
     int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
     const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const T *__restrict__ vA,
     const T *__restrict__ vB, const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta,
     unsigned a_bytes, unsigned b_bytes)
 {
-    __shared__ __attribute__((aligned(16))) char ring[D * RingEntry<B, G, T>::kBytes];
+    constexpr int kRing = D * RingEntry<B, G, T>::kBytes;   // per wave
+    __shared__ __attribute__((aligned(16))) char ring[W * kRing];
     const int64_t t = logical_workgroup(nwg_padded);
-    if (t >= ntiles) return;
-    tile_ring<B, G, D, T, BUF>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta, (lds_char_t *)ring,
-                               a_bytes, b_bytes);
+    if (t >= ntiles) return;   // uniform over the workgroup
+    const int w = W > 1 ? (int)(threadIdx.x >> 6) : 0;
+    tile_ring<B, G, D, T, BUF, W>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta,
+                                  (lds_char_t *)ring + w * kRing, a_bytes, b_bytes);
 }
 
 // ---------------------------------------------------------------- operand rounding
@@ -298,9 +300,11 @@ __global__ void k_group_tiles(int n, int G, int jt, int order, const int *__rest
 
 // One thread per tile: walk the union over the group's rows of P_A (k ascending);
 // keep k when some (i_a, k, j) triple exists.  MODE 0 counts entries and triples,
-// MODE 1 writes the entries.
+// MODE 1 writes the entries.  W = 2 (tiles shared by two waves): each entry is two
+// halves, one per wave and its jt / 2 columns, each with the A slots of the rows
+// that have a live triple in those columns and then those columns' B slots.
 template <int MODE>
-__global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restrict__ hdr,
+__global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, const int *__restrict__ hdr,
                                const int *__restrict__ tcols, const int *__restrict__ rpA,
                                const int *__restrict__ cA, const int *__restrict__ rpB,
                                const int *__restrict__ cB, const int *__restrict__ tmB,
@@ -309,7 +313,7 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restr
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
-    const int hs = G + G * jt, es = G + jt;
+    const int hs = G + G * jt, es = W * G + jt, jh = jt / W;
     const int *h = hdr + t * hs;
     int pa[kMaxRows], pae[kMaxRows], pb[64], pbe[64], jcol[64];
     for (int a = 0; a < G; ++a) {
@@ -350,24 +354,24 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restr
         // A row (B column) blocks with no live triple in this entry would only
         // meet zero blocks or outputs outside P_C: drop them, so that the kernels
         // neither copy nor multiply them
-        unsigned rowlive = 0;
+        unsigned rowlive[2] = {0u, 0u};
         unsigned long long collive = 0;
         for (int x = 0; x < jt; ++x) {
             if (bslot[x] < 0) continue;
             for (int a = 0; a < G; ++a)
                 if (aslot[a] >= 0 && h[G + a * jt + x] >= 0) {
-                    rowlive |= 1u << a;
+                    rowlive[x / jh] |= 1u << a;
                     collive |= 1ull << x;
                 }
         }
-        for (int a = 0; a < G; ++a)
-            if (!((rowlive >> a) & 1u)) aslot[a] = -1;
         for (int x = 0; x < jt; ++x)
             if (!((collive >> x) & 1ull)) bslot[x] = -1;
         if (MODE == 1) {
             int *e = ent + w * es;
-            for (int a = 0; a < G; ++a) e[a] = aslot[a];
-            for (int x = 0; x < jt; ++x) e[G + x] = bslot[x];
+            for (int hf = 0; hf < W; ++hf, e += G + jh) {
+                for (int a = 0; a < G; ++a) e[a] = ((rowlive[hf] >> a) & 1u) ? aslot[a] : -1;
+                for (int x = 0; x < jh; ++x) e[G + x] = bslot[hf * jh + x];
+            }
         }
         ++w;
         ++cnt;
@@ -376,8 +380,7 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, const int *__restr
     if (cnt & 1) {   // pad to an even count with an entry that multiplies nothing
         if (MODE == 1) {
             int *e = ent + w * es;
-            for (int a = 0; a < G; ++a) e[a] = -1;
-            for (int x = 0; x < jt; ++x) e[G + x] = -1;
+            for (int x = 0; x < es; ++x) e[x] = -1;
         }
         ++cnt;
     }
@@ -449,19 +452,20 @@ void launch_wg(hipStream_t st, const Plan *plan, const double *A, const double *
                                                          plan->ent.as<int>(), A, Bm, C, alpha, beta);
 }
 
-template <int B, int G, int D, class T = double>
+template <int B, int G, int D, class T = double, int W = 1>
 void launch_ring(hipStream_t st, const Plan *plan, const T *A, const T *Bm, double *C, double alpha, double beta,
                  const T *zblk, int64_t a_bytes, int64_t b_bytes)
 {
     const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
-    // variant 4: buffer copies when both operands fit a buffer resource; variant 3: 64-bit addresses
-    const bool buf = plan->variant == 4 && a_bytes <= (int64_t)kBufMaxBytes && b_bytes <= (int64_t)kBufMaxBytes;
+    // variants 4 and 5: buffer copies when both operands fit a buffer resource; else 64-bit addresses
+    const bool buf = (plan->variant == 4 || plan->variant == 5) && a_bytes <= (int64_t)kBufMaxBytes &&
+                     b_bytes <= (int64_t)kBufMaxBytes;
     if (buf)
-        k_product_ring<B, G, D, T, true><<<(unsigned)nwg_padded, 64, 0, st>>>(
+        k_product_ring<B, G, D, T, true, W><<<(unsigned)nwg_padded, 64 * W, 0, st>>>(
             plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
             plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta, (unsigned)a_bytes, (unsigned)b_bytes);
     else
-        k_product_ring<B, G, D, T, false><<<(unsigned)nwg_padded, 64, 0, st>>>(
+        k_product_ring<B, G, D, T, false, W><<<(unsigned)nwg_padded, 64 * W, 0, st>>>(
             plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
             plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta, 0u, 0u);
 }
@@ -471,6 +475,13 @@ void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *B
               double beta, const double *zblk, int64_t a_bytes, int64_t b_bytes)
 {
     if constexpr (B == 9 || B == 4) {
+        if (plan->variant == 5) {   // LDS rings, tiles shared by two waves
+            switch (plan->G) {
+                case 4: launch_ring<B, 4, 2, double, 2>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                case 8: launch_ring<B, 8, 2, double, 2>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                default: throw Error{BSM_EINVAL, "variant 5 takes 4 or 8 rows per tile"};
+            }
+        }
         if (plan->variant == 3 || plan->variant == 4) {   // LDS ring, depth 3 or 2
             const bool deep = plan->variant == 3;
             switch (plan->G) {
@@ -507,6 +518,13 @@ void launch_b32(hipStream_t st, const Plan *plan, const float *A, const float *B
                 double beta, const float *zblk, int64_t a_bytes, int64_t b_bytes)
 {
     if constexpr (B == 9 || B == 4) {
+        if (plan->variant == 5) {   // LDS rings, tiles shared by two waves, FP32 operands
+            switch (plan->G) {
+                case 4: launch_ring<B, 4, 2, float, 2>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                case 8: launch_ring<B, 8, 2, float, 2>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                default: throw Error{BSM_EINVAL, "variant 5 takes 4 or 8 rows per tile"};
+            }
+        }
         if (plan->variant == 3 || plan->variant == 4) {   // LDS ring, FP32 operands
             switch (plan->G) {
                 case 2: launch_ring<B, 2, 2, float>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
@@ -533,15 +551,17 @@ int default_rows_per_wave(int b) { return b >= 5 ? 4 : (b == 4 ? 4 : 2); }
 int default_variant(int b) { return (b == 9 || b == 4) ? 4 : 0; }
 
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
-                Plan *plan, int G)
+                Plan *plan, int G, int waves)
 {
     hipStream_t st = ctx->stream;
-    const int n = PC->natoms, jt = 64 / PC->b;
+    const int n = PC->natoms, jt = waves * (64 / PC->b);
     BSM_REQUIRE(G == 2 || G == 4 || G == 8 || G == kMaxRows, BSM_EINVAL, "rows per tile must be 2, 4, 8 or 16");
+    BSM_REQUIRE(waves == 1 || (waves == 2 && G <= 8), BSM_EINVAL, "two waves per tile take at most 8 rows");
     plan->G = G;
+    plan->waves = waves;
     plan->jt = jt;
     const int ng = (n + G - 1) / G;
-    const int hs = G + G * jt, es = G + jt;
+    const int hs = G + G * jt, es = waves * G + jt;
     DevBuf ntile(ctx, sizeof(int) * ng), ntile64(ctx, sizeof(int64_t) * ng), toff(ctx, sizeof(int64_t) * (ng + 1));
     k_group_union<<<(ng + 127) / 128, 128, 0, st>>>(n, G, PC->rowptr.as<int>(), PC->cols.as<int>(), jt,
                                                     ntile.as<int>());
@@ -597,7 +617,7 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
     unsigned long long ntri = 0;
     if (nt > 0) {
         const unsigned grid = (unsigned)((nt + 127) / 128);
-        k_tile_entries<0><<<grid, 128, 0, st>>>(nt, G, jt, plan->hdr.as<int>(), tcols.as<int>(), PA->rowptr.as<int>(),
+        k_tile_entries<0><<<grid, 128, 0, st>>>(nt, G, jt, waves, plan->hdr.as<int>(), tcols.as<int>(), PA->rowptr.as<int>(),
                                                 PA->cols.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
                                                 PB->tmap.as<int>(), nent.as<int64_t>(),
                                                 tri.as<unsigned long long>(), nullptr, nullptr);
@@ -607,7 +627,7 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
         BSM_HIP_TRY(hipStreamSynchronize(st));
         plan->ent = DevBuf(ctx, sizeof(int) * (size_t)((ne + 4) * es));   // 4 spare entries
         BSM_HIP_TRY(hipMemsetAsync(plan->ent.as<int>() + ne * es, 0xff, sizeof(int) * 4 * es, st));
-        k_tile_entries<1><<<grid, 128, 0, st>>>(nt, G, jt, plan->hdr.as<int>(), tcols.as<int>(), PA->rowptr.as<int>(),
+        k_tile_entries<1><<<grid, 128, 0, st>>>(nt, G, jt, waves, plan->hdr.as<int>(), tcols.as<int>(), PA->rowptr.as<int>(),
                                                 PA->cols.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
                                                 PB->tmap.as<int>(), nullptr, nullptr, plan->ebeg.as<int64_t>(),
                                                 plan->ent.as<int>());
@@ -658,6 +678,8 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     }
     BSM_REQUIRE(prec == BSM_F32 || prec == BSM_BF16, BSM_EINVAL, "precision must be F64, F32 or BF16");
     if (plan->G > 8) plan = get_plan_kind(ctx, PA, PB, PC, 0, default_rows_per_wave(PC->b));   // wave tiles
+    if (prec == BSM_BF16 && PC->b == 9 && plan->variant == 5)
+        plan = get_plan_kind(ctx, PA, PB, PC, 4, plan->G);   // the matrix cores take one-wave tiles
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
     if (prec == BSM_BF16 && PC->b == 9 && (plan->G == 4 || plan->G == 8) &&
@@ -735,7 +757,7 @@ Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B
     plan->cutoffs[2] = C->cutoff;
     plan->natoms = C->natoms;
     plan->b = C->b;
-    build_plan(ctx, A, B, C, plan.get(), G);
+    build_plan(ctx, A, B, C, plan.get(), G, variant == 5 ? 2 : 1);
     plan->variant = variant;
     Plan *raw = plan.get();
     ctx->plans[key] = std::move(plan);
@@ -747,7 +769,9 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
     int variant = ctx->product_variant >= 0 ? ctx->product_variant : default_variant(C->b);
     if (variant >= 2 && C->b != 9 && C->b != 4) variant = 0;
     int G = variant == 2 ? kMaxRows : (ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b));
-    if (variant == 4 && (C->b == 4 || C->b == 9) && ctx->rows_per_wave == 0) G = 8;   // measured best for the ring
+    if ((variant == 4 || variant == 5) && (C->b == 4 || C->b == 9) && ctx->rows_per_wave == 0)
+        G = 8;   // measured best for the ring
+    if (variant == 5 && G < 4) G = 4;   // two-wave tiles take 4 or 8 rows
     return get_plan_kind(ctx, A, B, C, variant, G);
 }
 

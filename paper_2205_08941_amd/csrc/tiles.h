@@ -564,21 +564,29 @@ constexpr unsigned kBufMaxBytes = 0xfffff000u;
 // BUF: copies through raw buffer resources over A and B (a_bytes, b_bytes, each
 // at most kBufMaxBytes): one scalar multiply and one vector add per block
 // instead of 64-bit address arithmetic and a zero-block select.
-template <int B, int G, int D, class T = double, bool BUF = false>
+// W = 2: the tile has 2 JT columns and two waves of one workgroup share it,
+// wave w taking columns w JT .. w JT + JT - 1 with its own ring.  Both waves walk
+// the tile's one list of k; each entry holds a half per wave (A slots of the
+// rows with outputs in that wave's columns, then its B slots), and a barrier per
+// step keeps the two waves on the same entry, so that the A blocks both copy
+// are fetched from HBM once and found in cache by the other wave.
+template <int B, int G, int D, class T = double, bool BUF = false, int W = 1>
 __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
                                  const int *__restrict__ ent, const T *__restrict__ vA, const T *__restrict__ vB,
                                  const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta,
                                  lds_char_t *ring, unsigned a_bytes = 0, unsigned b_bytes = 0)
 {
     using RE = RingEntry<B, G, T>;
+    static_assert(W == 1 || W == 2, "one or two waves per tile");
     constexpr int ESZ = (int)sizeof(T);
     constexpr int JT = 64 / B;
     constexpr int BB = B * B;
     constexpr int NA = (BB + 15) / 16;
-    constexpr int HS = G + G * JT;
-    constexpr int ES = G + JT;
+    constexpr int HS = G + G * JT * W;
+    constexpr int ES = (G + JT) * W;
     constexpr int NB = RE::kBlocks, DW = RE::kDwords, IPB = RE::kInstPerBlock, NI = RE::kInst;
     const int lane = threadIdx.x & 63;
+    const int w = W > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
     const int l16 = lane & 15;
     const int jl0 = lane / B, c = lane - jl0 * B;
     const bool lane_ok = jl0 < JT;
@@ -588,7 +596,7 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
     bool cact[G];
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-        cs[a] = lane_ok ? h[G + a * JT + jl] : -1;
+        cs[a] = lane_ok ? h[G + a * JT * W + w * JT + jl] : -1;
         cact[a] = cs[a] >= 0;
     }
     T acc[G][B];
@@ -602,7 +610,7 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
     const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
                        ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
     const int n = (int)(e1 - e0);
-    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES + w * (G + JT));
 
     // Copy an entry, given its slots, into ring position P; keep its A slots in
     // `asl`.  The DMA's immediate offset advances the global and the LDS address
@@ -703,6 +711,7 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
             constexpr int pn = (r + D - 1) % D;
             if constexpr (D == 3)
                 if (q0 + r >= n) return;
+            if constexpr (W > 1) __builtin_amdgcn_s_barrier();   // both waves at entry q0 + r
             load_slots(q0 + r + D, sbuf[r]);   // entry q0 + r's slots are no longer needed
             __builtin_amdgcn_sched_barrier(0);    // these loads first: their latency overlaps the copies
             issue(std::integral_constant<int, pn>{}, sbuf[pn], asl[pn]);

@@ -132,7 +132,8 @@ def test_product_parity(bsm, ctx, b):
 @pytest.mark.parametrize("variant,rows,system", [(0, 2, "si256_disp"), (0, 4, "si256_disp"), (0, 8, "si256_disp"),
                                                   (1, 2, "si256_disp"), (1, 4, "si256_disp"), (2, 0, "si256_disp"),
                                                   (2, 0, "si216_disp"), (3, 4, "si256_disp"), (3, 2, "si216_disp"),
-                                                  (4, 4, "si216_disp"), (4, 2, "si256_disp"), (4, 8, "si216_disp")])
+                                                  (4, 4, "si216_disp"), (4, 2, "si256_disp"), (4, 8, "si216_disp"),
+                                                  (5, 8, "si216_disp"), (5, 4, "si256_disp"), (5, 2, "si216_disp")])
 @pytest.mark.parametrize("b", [4, 9])
 def test_product_kernel_variants(bsm, b, variant, rows, system):
     """Every product kernel variant and rows-per-wave choice gives the oracle's result
@@ -156,7 +157,7 @@ def test_product_kernel_variants(bsm, b, variant, rows, system):
     ctx.close()
 
 
-@pytest.mark.parametrize("variant,rows", [(1, 4), (4, 4), (4, 8), (4, 2), (2, 0)])
+@pytest.mark.parametrize("variant,rows", [(1, 4), (4, 4), (4, 8), (4, 2), (2, 0), (5, 8), (5, 4)])
 @pytest.mark.parametrize("b", [4, 9])
 def test_product_degenerate_cases(bsm, b, variant, rows):
     """One atom (one tile, one entry padded to two); diagonal-only operands into a
@@ -194,7 +195,7 @@ def test_product_degenerate_cases(bsm, b, variant, rows):
     ctx.close()
 
 
-@pytest.mark.parametrize("variant,rows", [(4, 8), (4, 4), (3, 2), (1, 4), (2, 0), (0, 2)])
+@pytest.mark.parametrize("variant,rows", [(4, 8), (4, 4), (3, 2), (1, 4), (2, 0), (0, 2), (5, 8)])
 @pytest.mark.parametrize("b", [4, 9])
 def test_product_column_orders_agree(bsm, b, variant, rows):
     """Tiles over ascending columns (order 0) and over columns grouped by the rows
@@ -208,7 +209,7 @@ def test_product_column_orders_agree(bsm, b, variant, rows):
     data = [(synth.random_blocks(op[ra].nnz, b, 110 + n), synth.random_blocks(op[rb].nnz, b, 120 + n),
              synth.random_blocks(op[rc].nnz, b, 130 + n)) for n, (ra, rb, rc) in enumerate(cases)]
     out = {}
-    mfma = b == 9 and variant in (3, 4) and rows in (4, 8)   # BF16 on the matrix cores
+    mfma = b == 9 and variant in (3, 4, 5) and rows in (4, 8)   # BF16 on the matrix cores
     precs = (bsm.F64, bsm.F32, bsm.BF16) if mfma else (bsm.F64, bsm.F32)
     for order in (0, 1):
         ctx = bsm.Context(0)
@@ -460,7 +461,8 @@ def test_w_class_product_4096_sampled(bsm, ctx):
 
 # ------------------------------------------------------------------ mixed precision and diagnostics
 @pytest.mark.parametrize("prec,b,variant,rows", [(1, 4, -1, 0), (1, 9, -1, 0), (1, 9, -1, 4), (2, 4, -1, 0),
-                                                (2, 9, 1, 0), (2, 9, -1, 0), (2, 9, -1, 4), (2, 9, -1, 8)])
+                                                (2, 9, 1, 0), (2, 9, -1, 0), (2, 9, -1, 4), (2, 9, -1, 8),
+                                                (1, 9, 5, 0), (1, 4, 5, 0), (2, 4, 5, 0), (2, 9, 5, 0)])
 def test_mixed_product_parity(bsm, prec, b, variant, rows):
     """FP32 / BF16-rounded operands, FP32 accumulation.  VALU kernels: the oracle's
     result up to the FP64 epilogue (same rounding, same accumulation order).  BF16
@@ -472,7 +474,7 @@ def test_mixed_product_parity(bsm, prec, b, variant, rows):
     ctx = bsm.Context(0)
     ctx.set_product_variant(variant)
     ctx.set_rows_per_wave(rows)
-    mfma = prec == 2 and b == 9 and variant == -1
+    mfma = prec == 2 and b == 9 and variant in (-1, 5)
     s = SYSTEMS["si256_disp"]()
     say(f"mixed product prec={prec} b={b} variant={variant} rows={rows}")
     gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
