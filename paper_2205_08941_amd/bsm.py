@@ -254,7 +254,9 @@ class Context:
         _check(_lib.bsm_ctx_set_rows_per_wave(self.handle, int(rows)))
 
     def set_product_variant(self, variant: int) -> None:
-        """FP64 product kernel of plans built from now on (0: SGPR A, 1: DPP-broadcast A)."""
+        """Product kernel of plans built from now on: 0 SGPR A, 1 DPP-broadcast A, 2 workgroup
+        tiles, 3 and 4 LDS-DMA rings (4: buffer copies), 5 rings with tiles shared by two
+        waves, -1 the default (4 for b = 4 and 9).  Clears cached plans."""
         _check(_lib.bsm_ctx_set_product_variant(self.handle, int(variant)))
 
     def set_group_span(self, span: int) -> None:

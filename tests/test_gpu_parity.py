@@ -245,6 +245,35 @@ def test_product_column_orders_agree(bsm, b, variant, rows):
                 assert rel_err(out[1, n, prec], Co.blocks) < 1e-14, (ra, rb, rc)
 
 
+@pytest.mark.parametrize("b", [4, 9])
+def test_product_variants_bitwise_equal(bsm, b):
+    """Every FP64 kernel variant and tile height sums each output element's terms in
+    ascending (k, m) order with fused multiply-adds, so all give the same bits."""
+    s = SYSTEMS["si216_disp"]()
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
+    a = synth.random_blocks(op[14].nnz, b, 140)
+    bb = synth.random_blocks(op[8].nnz, b, 141)
+    c0 = synth.random_blocks(op[8].nnz, b, 142)
+    ref = None
+    for variant, rows in [(4, 8), (0, 2), (0, 8), (1, 4), (2, 0), (3, 4), (3, 2), (4, 4), (5, 8), (5, 4)]:
+        ctx = bsm.Context(0)
+        ctx.set_product_variant(variant)
+        ctx.set_rows_per_wave(rows)
+        say(f"bitwise variant={variant} rows={rows} b={b}")
+        gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (8, 14)}
+        C = gmat(bsm, gp[8], c0)
+        bsm.multiply_truncate(0.75, gmat(bsm, gp[14], a), gmat(bsm, gp[8], bb), -0.5, C)
+        got = host(C)
+        ctx.close()
+        if ref is None:
+            ref = got
+            Co = O.Matrix(op[8], b, c0.copy())
+            O.multiply_truncate(0.75, O.Matrix(op[14], b, a), O.Matrix(op[8], b, bb), -0.5, Co)
+            assert rel_err(ref, Co.blocks) < 1e-12
+        else:
+            assert np.array_equal(got, ref), (variant, rows)
+
+
 def test_column_order_rejects_bad_value(bsm, ctx):
     with pytest.raises(bsm.BSMError):
         ctx.set_column_order(2)
