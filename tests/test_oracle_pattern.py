@@ -1,4 +1,6 @@
-"""Oracle patterns against exact lattice counting and an independent brute force."""
+"""Oracle patterns against textbook shells, exact lattice counting and an independent brute force."""
+import os
+
 import numpy as np
 import pytest
 
@@ -21,13 +23,29 @@ def diamond_shell_count(r_over_quarter_a: float) -> int:
     return int(((even | odd) & (d2 < r_over_quarter_a ** 2)).sum())
 
 
+def textbook_shells():
+    """(squared distance in (a/4)^2, shell size, cumulative count) from tests/golden."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "diamond_shells.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    return [tuple(int(v) for v in r) for r in rows]
+
+
 def test_shell_count_helper_textbook_shells():
-    # first coordination shells of diamond: 4, 12, 12, 6 (plus the atom itself)
+    # the first coordination shells of diamond, counted just outside each shell
+    shells = textbook_shells()
+    assert [s[1] for s in shells] == [4, 12, 12, 6] and shells[-1][2] == 35
+    for d2, size, cum in shells:
+        assert diamond_shell_count(np.sqrt(d2) + 0.05) == cum
+        assert diamond_shell_count(np.sqrt(d2) - 0.05) == cum - size
+
+
+def test_oracle_rows_match_textbook_shells():
+    # the oracle's pattern on a periodic 4096-atom crystal, cut just outside each shell
+    pos, box, _ = synth.diamond_positions((8, 8, 8))
     q = synth.A_SI / 4
-    assert diamond_shell_count(2.5 / q) == 5
-    assert diamond_shell_count(4.0 / q) == 17
-    assert diamond_shell_count(5.0 / q) == 29
-    assert diamond_shell_count(5.5 / q) == 35
+    for d2, size, cum in textbook_shells():
+        P = O.create_pattern(pos, box, (np.sqrt(d2) + 0.05) * q)
+        assert np.all(np.diff(P.rowptr) == cum), d2
 
 
 @pytest.mark.parametrize("r", [6.0, 8.0, 10.0, 16.0])
