@@ -489,6 +489,34 @@ def test_w_class_product_4096_sampled(bsm, ctx):
         assert rel_err(g[sl], Co.blocks[sl]) < 1e-12, r
 
 
+def test_w_class_product_past_4gb_sampled(bsm, ctx):
+    """8192 atoms at 16 A: each operand holds 4.5 GB, past what the default kernel's
+    buffer copies address, so the same tiles run with 64-bit copy addresses; sampled
+    output rows against the oracle, and the flop count against the oracle's triples."""
+    pos, box, _ = synth.diamond_positions((16, 8, 8))
+    say("16 A product, 8192 atoms b=9: patterns")
+    P16 = gpat(bsm, ctx, pos, box, 16.0, 9)
+    o16 = O.create_pattern(pos, box, 16.0)
+    assert o16.nnz * 81 * 8 > 0xFFFFF000
+    rng = np.random.default_rng(2206)
+    x = rng.uniform(-1, 1, (o16.nnz, 9, 9))
+    y = rng.uniform(-1, 1, (o16.nnz, 9, 9))
+    say("16 A product, 8192 atoms b=9: GPU product")
+    X, Y = gmat(bsm, P16, x), gmat(bsm, P16, y)
+    C = bsm.Matrix(P16)
+    bsm.multiply_truncate(1.0, X, Y, 0.0, C)
+    g = host(C)
+    del X, Y, C
+    assert bsm.product_flops(P16, P16, P16) == 2.0 * 729 * O.count_triples(o16, o16, o16).sum()
+    rows = [0, 4095, 4096, 8191]
+    say("16 A product, 8192 atoms b=9: oracle rows", rows)
+    Co = O.Matrix(o16, 9)
+    for r in rows:
+        O.multiply_truncate(1.0, O.Matrix(o16, 9, x), O.Matrix(o16, 9, y), 0.0, Co, r, r + 1)
+        sl = slice(o16.rowptr[r], o16.rowptr[r + 1])
+        assert rel_err(g[sl], Co.blocks[sl]) < 1e-12, r
+
+
 # ------------------------------------------------------------------ mixed precision and diagnostics
 @pytest.mark.parametrize("prec,b,variant,rows", [(1, 4, -1, 0), (1, 9, -1, 0), (1, 9, -1, 4), (2, 4, -1, 0),
                                                 (2, 9, 1, 0), (2, 9, -1, 0), (2, 9, -1, 4), (2, 9, -1, 8),
