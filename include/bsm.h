@@ -162,6 +162,18 @@ int bsm_ctx_set_group_span(bsm_ctx ctx, int span);
  * pair entries differently and may differ in rounding.  order must be 0 or 1.  Clears cached plans (destroy batches first). */
 int bsm_ctx_set_column_order(bsm_ctx ctx, int order);
 
+/* Transposed plans for the default product kernel (variant 4, 4 or 8 rows per
+ * tile, b = 4 or 9) when A and B lie on different patterns: the product is also
+ * planned as C = (B^T A^T)^T, i.e. D = B^T A^T on P_C with blocks read transposed
+ * and D's blocks stored transposed at the slots of (j, i) (patterns are
+ * symmetric).  A wide A times a narrow B then walks the narrow pattern, leaving
+ * fewer lanes idle.  mode 0: never; 1 (default): the plan with the smaller
+ * estimated cost (rows multiplied + 4.5 x entries) is kept; 2: always when
+ * eligible.  Each element sums the same terms in the same order either way, so
+ * results are equal.  BF16 products on the matrix cores always use direct plans.
+ * Clears cached plans (destroy batches first). */
+int bsm_ctx_set_transposed_plans(bsm_ctx ctx, int mode);
+
 /* enable != 0 clears the statistics and starts recording; 0 stops. */
 int bsm_ctx_set_profiling(bsm_ctx ctx, int enable);
 /* Synchronises the stream, then writes up to `max` classes (most time first)

@@ -129,6 +129,7 @@ EXPORTS = {
     "bsm_ctx_set_product_variant": (c_int, [c_void_p, c_int]),
     "bsm_ctx_set_group_span": (c_int, [c_void_p, c_int]),
     "bsm_ctx_set_column_order": (c_int, [c_void_p, c_int]),
+    "bsm_ctx_set_transposed_plans": (c_int, [c_void_p, c_int]),
     "bsm_ctx_product_stats": (c_int, [c_void_p, ctypes.POINTER(_ProductStat), c_int, ctypes.POINTER(c_int)]),
     "bsm_create_pattern": (c_int, [c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_double), c_double,
                                    ctypes.POINTER(c_void_p)]),
@@ -267,6 +268,12 @@ class Context:
         """Tile columns of plans built from now on: 0 ascending, 1 grouped by the rows they
         hold outputs for (default); same products either way.  Clears cached plans."""
         _check(_lib.bsm_ctx_set_column_order(self.handle, int(order)))
+
+    def set_transposed_plans(self, mode: int) -> None:
+        """Products of A and B on different patterns: 0 direct plans only, 1 (default) the
+        cheaper of C = A B and C = (B^T A^T)^T, 2 the transposed plan whenever eligible.
+        Results are equal either way.  Clears cached plans."""
+        _check(_lib.bsm_ctx_set_transposed_plans(self.handle, int(mode)))
 
     def product_stats(self) -> list:
         """Per (P_A, P_B, P_C) class: launches, algorithmic flops, event milliseconds."""

@@ -269,6 +269,19 @@ int bsm_ctx_set_column_order(bsm_ctx ctx, int order)
     BSM_API_END
 }
 
+int bsm_ctx_set_transposed_plans(bsm_ctx ctx, int mode)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
+    BSM_REQUIRE(mode >= 0 && mode <= 2, BSM_EINVAL, "mode must be 0, 1 or 2");
+    BSM_HIP_TRY(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.retire_profile([](const Plan *) { return true; });
+    ctx->c.plans.clear();
+    ctx->c.transposed_plans = mode;
+    return BSM_OK;
+    BSM_API_END
+}
+
 int bsm_ctx_set_profiling(bsm_ctx ctx, int enable)
 {
     BSM_API_BEGIN

@@ -64,6 +64,7 @@ struct Plan {
     int variant = 0;            // 0: A through SGPRs, 1: A in VGPRs with DPP broadcast, 2: workgroup tiles,
                                 // 3, 4: LDS-DMA rings, 5: rings with tiles shared by two waves
     int waves = 1;              // waves per tile (2 for variant 5)
+    int transposed = 0;         // 1: computes C^T = B^T A^T (operands swapped, blocks read and C written transposed)
     int jt = 0;                 // output block columns per tile (waves * 64 / b)
     int64_t ntiles = 0;
     int64_t nentries = 0;
@@ -74,6 +75,7 @@ struct Plan {
     DevBuf ent;                 // int [nentries][waves * G + jt]: per wave A slots, then its B slots
     double flops = 0.0;         // algorithmic: 2 b^3 per block triple
     int64_t triples = 0;
+    int64_t rowwork = 0;        // rows multiplied, summed over entries (and waves)
 };
 
 class Context {
@@ -90,7 +92,9 @@ class Context {
     int column_order = 1;       // tile columns: 0 ascending, 1 grouped by the rows they hold outputs for
     // derived patterns (same atoms, another cutoff), owned here, keyed by (source id, cutoff)
     std::map<std::pair<uint64_t, double>, bsm_pattern_s *> derived;
-    std::map<std::tuple<uint64_t, uint64_t, uint64_t, int, int>, std::unique_ptr<Plan>> plans;   // (A, B, C, variant, rows)
+    // (A, B, C, variant, rows, transposed plans allowed)
+    std::map<std::tuple<uint64_t, uint64_t, uint64_t, int, int, int>, std::unique_ptr<Plan>> plans;
+    int transposed_plans = 1;   // 0 never, 1 when estimated cheaper, 2 whenever allowed
     // reduction scratch
     DevBuf red_partials;        // double[kRedBlocks * kRedSlots]
     DevBuf err_flag;            // int
@@ -168,14 +172,14 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
 // A plan of a given kernel variant (0: SGPR, 1: DPP wave tiles, 2: workgroup tiles, 3 and 4: LDS-DMA
 // rings, 5: rings with tiles shared by two waves) and rows per tile.
 Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C,
-                    int variant, int G);
+                    int variant, int G, bool allow_transposed = false);
 
 // ---------------------------------------------------------------- launches
 void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
                         const double *A, const bsm_pattern_s *PB, const double *B, double beta,
                         const bsm_pattern_s *PC, double *C);
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
-                Plan *plan, int G, int waves);
+                Plan *plan, int G, int waves, int transposed = 0);
 // prec BSM_F64: the FP64 product; BSM_F32 / BSM_BF16: operands rounded to that
 // precision, FP32 accumulation, FP64 result.
 void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha, const bsm_pattern_s *PA,

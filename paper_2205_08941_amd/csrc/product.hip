@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_product_wg(
 
 // One wave tile per one-wave workgroup, operands through a per-wave LDS ring
 // (BUF: copied through buffer resources of a_bytes and b_bytes).
-template <int B, int G, int D, class T = double, bool BUF = false, int W = 1>
+template <int B, int G, int D, class T = double, bool BUF = false, int W = 1, int TR = 0>
 __global__ __launch_bounds__(64 * W) void k_product_ring(
     int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
     const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const T *__restrict__ vA,
@@ -97,8 +97,8 @@ __global__ __launch_bounds__(64 * W) void k_product_ring(
     const int64_t t = logical_workgroup(nwg_padded);
     if (t >= ntiles) return;   // uniform over the workgroup
     const int w = W > 1 ? (int)(threadIdx.x >> 6) : 0;
-    tile_ring<B, G, D, T, BUF, W>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta,
-                                  (lds_char_t *)ring + w * kRing, a_bytes, b_bytes);
+    tile_ring<B, G, D, T, BUF, W, TR>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta,
+                                      (lds_char_t *)ring + w * kRing, a_bytes, b_bytes);
 }
 
 // ---------------------------------------------------------------- operand rounding
@@ -304,11 +304,12 @@ __global__ void k_group_tiles(int n, int G, int jt, int order, const int *__rest
 // halves, one per wave and its jt / 2 columns, each with the A slots of the rows
 // that have a live triple in those columns and then those columns' B slots.
 template <int MODE>
-__global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, const int *__restrict__ hdr,
+__global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, int tr, const int *__restrict__ hdr,
                                const int *__restrict__ tcols, const int *__restrict__ rpA,
-                               const int *__restrict__ cA, const int *__restrict__ rpB,
-                               const int *__restrict__ cB, const int *__restrict__ tmB,
-                               int64_t *__restrict__ nent, unsigned long long *__restrict__ triples,
+                               const int *__restrict__ cA, const int *__restrict__ tmA,
+                               const int *__restrict__ rpB, const int *__restrict__ cB,
+                               const int *__restrict__ tmB, int64_t *__restrict__ nent,
+                               unsigned long long *__restrict__ triples, unsigned long long *__restrict__ rowwork,
                                const int64_t *__restrict__ ebeg, int *__restrict__ ent)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -329,7 +330,7 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, const int *
     }
     int64_t w = (MODE == 1) ? ebeg[t] : 0;
     int64_t cnt = 0;
-    unsigned long long tri = 0;
+    unsigned long long tri = 0, rw = 0;
     while (true) {
         int k = 0x7fffffff;
         for (int a = 0; a < G; ++a)
@@ -338,7 +339,7 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, const int *
         int aslot[kMaxRows];
         for (int a = 0; a < G; ++a) {
             aslot[a] = -1;
-            if (pa[a] < pae[a] && cA[pa[a]] == k) aslot[a] = pa[a]++;
+            if (pa[a] < pae[a] && cA[pa[a]] == k) aslot[a] = tr ? tmA[pa[a]++] : pa[a]++;   // tr: slot of (k, i)
         }
         int bslot[64];
         int ntri = 0;
@@ -346,7 +347,7 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, const int *
             bslot[x] = -1;
             if (jcol[x] < 0) continue;
             while (pb[x] < pbe[x] && cB[pb[x]] < k) ++pb[x];
-            if (pb[x] < pbe[x] && cB[pb[x]] == k) bslot[x] = tmB[pb[x]];   // slot of (k, j)
+            if (pb[x] < pbe[x] && cB[pb[x]] == k) bslot[x] = tr ? pb[x] : tmB[pb[x]];   // (k, j); tr: (j, k)
             if (bslot[x] < 0) continue;
             for (int a = 0; a < G; ++a) ntri += (aslot[a] >= 0 && h[G + a * jt + x] >= 0) ? 1 : 0;
         }
@@ -376,6 +377,7 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, const int *
         ++w;
         ++cnt;
         tri += ntri;
+        for (int hf = 0; hf < W; ++hf) rw += __popc(rowlive[hf]);   // rows multiplied
     }
     if (cnt & 1) {   // pad to an even count with an entry that multiplies nothing
         if (MODE == 1) {
@@ -386,8 +388,19 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, const int *
     }
     if (MODE == 0) {
         nent[t] = cnt;
-        atomicAdd(triples, tri);   // integer: order-independent
+        atomicAdd(triples, tri);   // integers: order-independent
+        atomicAdd(rowwork, rw);
     }
+}
+
+// One thread per tile of a transposed plan: C slots of (i, j) -> slots of (j, i).
+__global__ void k_map_cslots(int64_t ntiles, int G, int jt, const int *__restrict__ tmC, int *__restrict__ hdr)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int *h = hdr + t * (G + G * jt) + G;
+    for (int x = 0; x < G * jt; ++x)
+        if (h[x] >= 0) h[x] = tmC[h[x]];
 }
 
 __global__ __launch_bounds__(1024) void k_scan64(int64_t n, const int64_t *__restrict__ in, int64_t *__restrict__ out)
@@ -452,22 +465,38 @@ void launch_wg(hipStream_t st, const Plan *plan, const double *A, const double *
                                                          plan->ent.as<int>(), A, Bm, C, alpha, beta);
 }
 
-template <int B, int G, int D, class T = double, int W = 1>
-void launch_ring(hipStream_t st, const Plan *plan, const T *A, const T *Bm, double *C, double alpha, double beta,
-                 const T *zblk, int64_t a_bytes, int64_t b_bytes)
+template <int B, int G, int D, class T = double, int W = 1, int TR = 0>
+void launch_ring_t(hipStream_t st, const Plan *plan, const T *A, const T *Bm, double *C, double alpha, double beta,
+                   const T *zblk, int64_t a_bytes, int64_t b_bytes)
 {
     const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
     // variants 4 and 5: buffer copies when both operands fit a buffer resource; else 64-bit addresses
     const bool buf = (plan->variant == 4 || plan->variant == 5) && a_bytes <= (int64_t)kBufMaxBytes &&
                      b_bytes <= (int64_t)kBufMaxBytes;
     if (buf)
-        k_product_ring<B, G, D, T, true, W><<<(unsigned)nwg_padded, 64 * W, 0, st>>>(
+        k_product_ring<B, G, D, T, true, W, TR><<<(unsigned)nwg_padded, 64 * W, 0, st>>>(
             plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
             plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta, (unsigned)a_bytes, (unsigned)b_bytes);
     else
-        k_product_ring<B, G, D, T, false, W><<<(unsigned)nwg_padded, 64 * W, 0, st>>>(
+        k_product_ring<B, G, D, T, false, W, TR><<<(unsigned)nwg_padded, 64 * W, 0, st>>>(
             plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
             plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta, 0u, 0u);
+}
+
+// Transposed plans (one-wave tiles of 4 or 8 rows, depth 2) compute C^T = B^T A^T:
+// the kernel's A operand is B and its B operand is A.
+template <int B, int G, int D, class T = double, int W = 1>
+void launch_ring(hipStream_t st, const Plan *plan, const T *A, const T *Bm, double *C, double alpha, double beta,
+                 const T *zblk, int64_t a_bytes, int64_t b_bytes)
+{
+    if constexpr (W == 1 && D == 2 && (G == 4 || G == 8)) {
+        if (plan->transposed) {
+            launch_ring_t<B, G, D, T, W, 1>(st, plan, Bm, A, C, alpha, beta, zblk, b_bytes, a_bytes);
+            return;
+        }
+    }
+    if (plan->transposed) throw Error{BSM_EINVAL, "transposed plan without a transposed kernel"};
+    launch_ring_t<B, G, D, T, W, 0>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes);
 }
 
 template <int B>
@@ -551,8 +580,12 @@ int default_rows_per_wave(int b) { return b >= 5 ? 4 : (b == 4 ? 4 : 2); }
 int default_variant(int b) { return (b == 9 || b == 4) ? 4 : 0; }
 
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
-                Plan *plan, int G, int waves)
+                Plan *plan, int G, int waves, int transposed)
 {
+    // transposed: plan D = B^T A^T on P_C (C = D^T); the kernel's A operand is B
+    // (rows over P_B, which is symmetric), its B operand is A
+    BSM_REQUIRE(!transposed || waves == 1, BSM_EINVAL, "transposed plans use one-wave tiles");
+    if (transposed) std::swap(PA, PB);
     hipStream_t st = ctx->stream;
     const int n = PC->natoms, jt = waves * (64 / PC->b);
     BSM_REQUIRE(G == 2 || G == 4 || G == 8 || G == kMaxRows, BSM_EINVAL, "rows per tile must be 2, 4, 8 or 16");
@@ -609,27 +642,30 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
                                                         tcols.as<int>(), cbuf.as<int>(), mbuf.as<int>());
         BSM_HIP_TRY(hipStreamSynchronize(st));   // before the sort buffers are freed
     }
-    DevBuf nent(ctx, sizeof(int64_t) * (size_t)std::max<int64_t>(1, nt)), tri(ctx, sizeof(unsigned long long));
+    DevBuf nent(ctx, sizeof(int64_t) * (size_t)std::max<int64_t>(1, nt)), tri(ctx, 2 * sizeof(unsigned long long));
     plan->ebeg = DevBuf(ctx, sizeof(int64_t) * (size_t)(nt + 1));
-    BSM_HIP_TRY(hipMemsetAsync(tri.ptr, 0, sizeof(unsigned long long), st));
+    BSM_HIP_TRY(hipMemsetAsync(tri.ptr, 0, 2 * sizeof(unsigned long long), st));
     BSM_HIP_TRY(hipMemsetAsync(plan->ebeg.ptr, 0, sizeof(int64_t) * (size_t)(nt + 1), st));
     int64_t ne = 0;
-    unsigned long long ntri = 0;
+    unsigned long long ntri[2] = {0, 0};   // triples, rows multiplied
     if (nt > 0) {
         const unsigned grid = (unsigned)((nt + 127) / 128);
-        k_tile_entries<0><<<grid, 128, 0, st>>>(nt, G, jt, waves, plan->hdr.as<int>(), tcols.as<int>(), PA->rowptr.as<int>(),
-                                                PA->cols.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
+        k_tile_entries<0><<<grid, 128, 0, st>>>(nt, G, jt, waves, transposed, plan->hdr.as<int>(), tcols.as<int>(),
+                                                PA->rowptr.as<int>(), PA->cols.as<int>(), PA->tmap.as<int>(),
+                                                PB->rowptr.as<int>(), PB->cols.as<int>(),
                                                 PB->tmap.as<int>(), nent.as<int64_t>(),
-                                                tri.as<unsigned long long>(), nullptr, nullptr);
+                                                tri.as<unsigned long long>(), tri.as<unsigned long long>() + 1,
+                                                nullptr, nullptr);
         k_scan64<<<1, 1024, 0, st>>>(nt, nent.as<int64_t>(), plan->ebeg.as<int64_t>());
         BSM_HIP_TRY(hipMemcpyAsync(&ne, plan->ebeg.as<int64_t>() + nt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        BSM_HIP_TRY(hipMemcpyAsync(&ntri, tri.ptr, sizeof(ntri), hipMemcpyDeviceToHost, st));
+        BSM_HIP_TRY(hipMemcpyAsync(ntri, tri.ptr, sizeof(ntri), hipMemcpyDeviceToHost, st));
         BSM_HIP_TRY(hipStreamSynchronize(st));
         plan->ent = DevBuf(ctx, sizeof(int) * (size_t)((ne + 4) * es));   // 4 spare entries
         BSM_HIP_TRY(hipMemsetAsync(plan->ent.as<int>() + ne * es, 0xff, sizeof(int) * 4 * es, st));
-        k_tile_entries<1><<<grid, 128, 0, st>>>(nt, G, jt, waves, plan->hdr.as<int>(), tcols.as<int>(), PA->rowptr.as<int>(),
-                                                PA->cols.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
-                                                PB->tmap.as<int>(), nullptr, nullptr, plan->ebeg.as<int64_t>(),
+        k_tile_entries<1><<<grid, 128, 0, st>>>(nt, G, jt, waves, transposed, plan->hdr.as<int>(), tcols.as<int>(),
+                                                PA->rowptr.as<int>(), PA->cols.as<int>(), PA->tmap.as<int>(),
+                                                PB->rowptr.as<int>(), PB->cols.as<int>(),
+                                                PB->tmap.as<int>(), nullptr, nullptr, nullptr, plan->ebeg.as<int64_t>(),
                                                 plan->ent.as<int>());
         BSM_HIP_TRY(hipGetLastError());
     } else {
@@ -638,8 +674,15 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
     }
     BSM_HIP_TRY(hipStreamSynchronize(st));
     plan->nentries = ne;
-    plan->triples = (int64_t)ntri;
-    plan->flops = 2.0 * (double)PC->b * PC->b * PC->b * (double)ntri;
+    plan->triples = (int64_t)ntri[0];
+    plan->rowwork = (int64_t)ntri[1];
+    plan->flops = 2.0 * (double)PC->b * PC->b * PC->b * (double)ntri[0];
+    plan->transposed = transposed;
+    if (transposed && nt > 0) {   // outputs go to the slot of (j, i)
+        k_map_cslots<<<(unsigned)((nt + 127) / 128), 128, 0, st>>>(nt, G, jt, PC->tmap.as<int>(), plan->hdr.as<int>());
+        BSM_HIP_TRY(hipGetLastError());
+        BSM_HIP_TRY(hipStreamSynchronize(st));
+    }
 }
 
 void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
@@ -678,8 +721,8 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     }
     BSM_REQUIRE(prec == BSM_F32 || prec == BSM_BF16, BSM_EINVAL, "precision must be F64, F32 or BF16");
     if (plan->G > 8) plan = get_plan_kind(ctx, PA, PB, PC, 0, default_rows_per_wave(PC->b));   // wave tiles
-    if (prec == BSM_BF16 && PC->b == 9 && plan->variant == 5)
-        plan = get_plan_kind(ctx, PA, PB, PC, 4, plan->G);   // the matrix cores take one-wave tiles
+    if (prec == BSM_BF16 && PC->b == 9 && (plan->variant == 5 || plan->transposed))
+        plan = get_plan_kind(ctx, PA, PB, PC, 4, plan->G);   // the matrix cores take direct one-wave tiles
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
     if (prec == BSM_BF16 && PC->b == 9 && (plan->G == 4 || plan->G == 8) &&
@@ -742,23 +785,41 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     }
 }
 
+// Estimated cost of a plan for the ring kernels: rows multiplied plus the
+// fixed work of an entry (copies, waits, B reads), worth about 4.5 rows by
+// measurement.
+static double plan_cost(const Plan *p) { return (double)p->rowwork + 4.5 * (double)p->nentries; }
+
 Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C,
-                    int variant, int G)
+                    int variant, int G, bool allow_transposed)
 {
-    auto key = std::make_tuple(A->id, B->id, C->id, variant, G);
+    // C = (B^T A^T)^T is an option for the default ring kernel when A and B lie on
+    // different patterns (all patterns are symmetric): a wide A times a narrow B
+    // then walks the narrow pattern, with far fewer idle lanes
+    const bool try_t = allow_transposed && ctx->transposed_plans > 0 && variant == 4 && (G == 4 || G == 8) &&
+                       (C->b == 4 || C->b == 9) && A->id != B->id;
+    auto key = std::make_tuple(A->id, B->id, C->id, variant, G, try_t ? 1 : 0);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) return it->second.get();
-    std::unique_ptr<Plan> plan(new Plan());
-    plan->ids[0] = A->id;
-    plan->ids[1] = B->id;
-    plan->ids[2] = C->id;
-    plan->cutoffs[0] = A->cutoff;
-    plan->cutoffs[1] = B->cutoff;
-    plan->cutoffs[2] = C->cutoff;
-    plan->natoms = C->natoms;
-    plan->b = C->b;
-    build_plan(ctx, A, B, C, plan.get(), G, variant == 5 ? 2 : 1);
-    plan->variant = variant;
+    auto make = [&](int transposed) {
+        std::unique_ptr<Plan> plan(new Plan());
+        plan->ids[0] = A->id;
+        plan->ids[1] = B->id;
+        plan->ids[2] = C->id;
+        plan->cutoffs[0] = A->cutoff;
+        plan->cutoffs[1] = B->cutoff;
+        plan->cutoffs[2] = C->cutoff;
+        plan->natoms = C->natoms;
+        plan->b = C->b;
+        build_plan(ctx, A, B, C, plan.get(), G, variant == 5 ? 2 : 1, transposed);
+        plan->variant = variant;
+        return plan;
+    };
+    std::unique_ptr<Plan> plan = ctx->transposed_plans == 2 && try_t ? make(1) : make(0);
+    if (try_t && ctx->transposed_plans == 1) {
+        std::unique_ptr<Plan> alt = make(1);
+        if (plan_cost(alt.get()) < plan_cost(plan.get())) plan = std::move(alt);
+    }
     Plan *raw = plan.get();
     ctx->plans[key] = std::move(plan);
     return raw;
@@ -772,7 +833,7 @@ Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, con
     if ((variant == 4 || variant == 5) && (C->b == 4 || C->b == 9) && ctx->rows_per_wave == 0)
         G = 8;   // measured best for the ring
     if (variant == 5 && G < 4) G = 4;   // two-wave tiles take 4 or 8 rows
-    return get_plan_kind(ctx, A, B, C, variant, G);
+    return get_plan_kind(ctx, A, B, C, variant, G, true);
 }
 
 }  // namespace bsm

@@ -13,6 +13,14 @@ namespace bsm {
 // address is uniform.
 template <class T> using const_as4 = const __attribute__((address_space(4))) T;
 
+// alpha s + beta c with each operation rounded on its own (no fused contraction
+// that a compiler may apply one way in one kernel and another way in the next),
+// so that every product kernel stores the same bits for the same sums.
+__device__ inline double scale_add(double alpha, double s, double beta, double c)
+{
+    return __dadd_rn(__dmul_rn(alpha, s), __dmul_rn(beta, c));
+}
+
 template <int B, int G, class T>
 __device__ inline void multiply_entry(const_as4<int> *entu, int64_t q, const_as4<T> *vAu, const T (&bv)[B],
                                       bool bact, const bool (&cact)[G], T (&acc)[G][B])
@@ -119,7 +127,7 @@ __device__ inline void tile_sgpr(int64_t tile, const int *__restrict__ hdr, cons
             for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r] + beta * cp[r * B];
+            for (int r = 0; r < B; ++r) cp[r * B] = scale_add(alpha, (double)acc[a][r], beta, cp[r * B]);
         }
     }
 }
@@ -344,7 +352,7 @@ __device__ inline void tile_dpp(int64_t tile, const int *__restrict__ hdr, const
             for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
+            for (int r = 0; r < B; ++r) cp[r * B] = scale_add(alpha, acc[a][r], beta, cp[r * B]);
         }
     }
 }
@@ -485,7 +493,7 @@ __device__ inline void tile_wg(int64_t tile, const int *__restrict__ hdr, const 
             for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * acc[a][r] + beta * cp[r * B];
+            for (int r = 0; r < B; ++r) cp[r * B] = scale_add(alpha, acc[a][r], beta, cp[r * B]);
         }
     }
 }
@@ -570,7 +578,12 @@ constexpr unsigned kBufMaxBytes = 0xfffff000u;
 // rows with outputs in that wave's columns, then its B slots), and a barrier per
 // step keeps the two waves on the same entry, so that the A blocks both copy
 // are fetched from HBM once and found in cache by the other wave.
-template <int B, int G, int D, class T = double, bool BUF = false, int W = 1>
+// TR = 1: the tile computes D = B^T A^T on P_C for C = D^T (the launch passes
+// the operands swapped, the plan holds their slots): every block is read
+// transposed from the ring and the result is stored transposed, at the slot of
+// (j, i) that the plan's header gives.  Each element sums the same terms in the
+// same order as the direct product.
+template <int B, int G, int D, class T = double, bool BUF = false, int W = 1, int TR = 0>
 __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
                                  const int *__restrict__ ent, const T *__restrict__ vA, const T *__restrict__ vB,
                                  const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta,
@@ -578,6 +591,7 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
 {
     using RE = RingEntry<B, G, T>;
     static_assert(W == 1 || W == 2, "one or two waves per tile");
+    static_assert(TR == 0 || W == 1, "transposed products use one-wave tiles");
     constexpr int ESZ = (int)sizeof(T);
     constexpr int JT = 64 / B;
     constexpr int BB = B * B;
@@ -653,15 +667,16 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
     auto compute = [&](auto P, const int (&as)[G]) {
         const lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
         T bv[B];
-        lds_const_t<T> *bp = (lds_const_t<T> *)(slot + (G + jl) * (BB * ESZ)) + c;
+        lds_const_t<T> *bp = (lds_const_t<T> *)(slot + (G + jl) * (BB * ESZ)) + (TR ? c * B : c);
 #pragma unroll
-        for (int m = 0; m < B; ++m) bv[m] = bp[m * B];
+        for (int m = 0; m < B; ++m) bv[m] = bp[TR ? m : m * B];   // element (m, c) of the B operand
         auto read_row = [&](T (&xr)[NA], int a) {
             lds_const_t<T> *ap = (lds_const_t<T> *)(slot + a * (BB * ESZ));
 #pragma unroll
             for (int v = 0; v < NA; ++v) {
                 int idx = l16 + 16 * v;
                 if (idx >= BB) idx -= BB;
+                if constexpr (TR) idx = (idx % B) * B + idx / B;   // element (r, m) of the A operand
                 xr[v] = ap[idx];
             }
         };
@@ -726,13 +741,15 @@ __device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, cons
 #pragma unroll
     for (int a = 0; a < G; ++a) {
         if (!cact[a]) continue;
-        double *cp = vC + (int64_t)cs[a] * BB + c;
+        // TR: element (r, c) of D is element (c, r) of C's block
+        double *cp = vC + (int64_t)cs[a] * BB + (TR ? c * B : c);
+        constexpr int RS = TR ? 1 : B;
         if (beta == 0.0) {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r];
+            for (int r = 0; r < B; ++r) cp[r * RS] = alpha * (double)acc[a][r];
         } else {
 #pragma unroll
-            for (int r = 0; r < B; ++r) cp[r * B] = alpha * (double)acc[a][r] + beta * cp[r * B];
+            for (int r = 0; r < B; ++r) cp[r * RS] = scale_add(alpha, (double)acc[a][r], beta, cp[r * RS]);
         }
     }
 }
@@ -892,8 +909,7 @@ __device__ inline void tile_mfma_bf16(int64_t tile, const int *__restrict__ hdr,
                 const int cs = h[G + a * JT + jj];
                 if (cs < 0) continue;
                 double *cp = vC + (int64_t)cs * BB + p * B + q;
-                const double v = alpha * (double)acc[t][u][i];
-                *cp = beta == 0.0 ? v : v + beta * *cp;
+                *cp = beta == 0.0 ? alpha * (double)acc[t][u][i] : scale_add(alpha, (double)acc[t][u][i], beta, *cp);
             }
         }
     }

@@ -275,6 +275,55 @@ def test_product_variants_bitwise_equal(bsm, b):
             assert np.array_equal(got, ref), (variant, rows)
 
 
+@pytest.mark.parametrize("rows", [8, 4])
+@pytest.mark.parametrize("b", [4, 9])
+def test_transposed_plans_agree(bsm, b, rows):
+    """Products planned as C = (B^T A^T)^T (blocks read transposed, C's blocks written
+    at the transposed slots) equal the direct products element by element in FP64
+    and FP32 (the same terms in the same order), on classes where A and B lie on
+    different patterns; both match the oracle.  BF16 on the matrix cores keeps
+    direct plans."""
+    s = SYSTEMS["si216_disp"]()
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
+    cases = [(14, 8, 6), (14, 6, 8), (8, 14, 8), (6, 8, 14), (14, 8, 14)]
+    data = [(synth.random_blocks(op[ra].nnz, b, 150 + n), synth.random_blocks(op[rb].nnz, b, 160 + n),
+             synth.random_blocks(op[rc].nnz, b, 170 + n)) for n, (ra, rb, rc) in enumerate(cases)]
+    precs = (bsm.F64, bsm.F32, bsm.BF16) if b == 9 else (bsm.F64, bsm.F32)
+    out = {}
+    for mode in (0, 2):
+        ctx = bsm.Context(0)
+        ctx.set_rows_per_wave(rows)
+        ctx.set_transposed_plans(mode)
+        say(f"transposed plans mode={mode} rows={rows} b={b}")
+        gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
+        for n, (ra, rb, rc) in enumerate(cases):
+            a, bb, c0 = data[n]
+            for prec in precs:
+                C = gmat(bsm, gp[rc], c0)
+                bsm.multiply_truncate_prec(prec, 1.25, gmat(bsm, gp[ra], a), gmat(bsm, gp[rb], bb), -0.5, C)
+                out[mode, n, prec] = host(C)
+        ctx.close()
+    for n, (ra, rb, rc) in enumerate(cases):
+        a, bb, c0 = data[n]
+        for prec in precs:
+            if prec != bsm.BF16:
+                assert np.array_equal(out[0, n, prec], out[2, n, prec]), (ra, rb, rc, prec)
+            Co = O.Matrix(op[rc], b, c0.copy())
+            if prec == bsm.F64:
+                O.multiply_truncate(1.25, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), -0.5, Co)
+                tol = 1e-12
+            else:
+                O.multiply_truncate_mixed(prec, 1.25, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), -0.5, Co)
+                tol = 2e-6 if prec == bsm.BF16 else 1e-14
+            for mode in (0, 2):
+                assert rel_err(out[mode, n, prec], Co.blocks) < tol, (mode, ra, rb, rc, prec)
+
+
+def test_transposed_plans_reject_bad_mode(bsm, ctx):
+    with pytest.raises(bsm.BSMError):
+        ctx.set_transposed_plans(3)
+
+
 def test_column_order_rejects_bad_value(bsm, ctx):
     with pytest.raises(bsm.BSMError):
         ctx.set_column_order(2)
