@@ -222,7 +222,10 @@ int bsm_dot(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, double *out);
  * P_B of A_ik B_kj; pairs outside P_C are never formed (the truncation of a
  * product back to its cutoff pattern, the paper's local sparse operations,
  * Background).  beta == 0 ignores C's old contents.  The product plan for
- * (P_A, P_B, P_C) is built on first use and cached in the context.
+ * (P_A, P_B, P_C) is built on first use and cached in the context (tiles of
+ * rows x columns of C with their lists of k; see bsm_ctx_set_column_order and
+ * bsm_ctx_set_transposed_plans).  With beta != 0 each element is
+ * alpha s + beta c, each product and the sum rounded separately.
  * Asynchronous.  Errors: BSM_EPATTERN (natoms or b differ), BSM_EINVAL (C's
  * blocks alias A's or B's, dtype not F64), BSM_ENOMEM, BSM_EHIP. */
 int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *B,
