@@ -191,6 +191,13 @@ int default_rows_per_wave(int b);
 // on one pattern, B_n all on one pattern.  Results to host `out`.  Synchronises.
 void trace_products(Context *ctx, int count, const bsm_pattern_s *PA, const double *const *A,
                     const bsm_pattern_s *PB, const double *const *B, double *out);
+// The LNV's fixed trace sets on one pattern, from the distinct matrices only
+// (each loaded once): kTracesEnergy, A = {X, W}, B = {Y, X}: Tr XY, Tr WY,
+// Tr XX, Tr WX; kTracesLineSearch, A = {X_D, X, M1, W, Q}, B = {Y, Y_D, X_D, X}:
+// the 15 traces of the line-search polynomials.  Same bits as trace_products.
+enum { kTracesEnergy = 0, kTracesLineSearch = 1 };
+void trace_set(Context *ctx, int kind, const bsm_pattern_s *P, const double *const *A, const double *const *B,
+               double *out);
 // <A_n, B_n> (same pattern) for up to kRedSlots pairs.  Synchronises.
 void dots(Context *ctx, int count, const bsm_pattern_s *P, const double *const *A,
           const double *const *B, double *out);

@@ -171,9 +171,9 @@ struct lnv_state_s {
         mul(1.0, PL, L, PS, S, 0.0, X.p, X.d());
         mul(1.0, PL, L, PH, H, 0.0, Y.p, Y.d());
         mul(X, X, W);
-        double tr[4];
-        const double *a[4] = {X.d(), W.d(), X.d(), W.d()}, *b[4] = {Y.d(), Y.d(), X.d(), X.d()};
-        trace_products(c, 4, X.p, a, X.p, b, tr);
+        double tr[4];   // Tr XY, Tr WY, Tr XX, Tr WX
+        const double *a[2] = {X.d(), W.d()}, *b[2] = {Y.d(), X.d()};
+        trace_set(c, kTracesEnergy, X.p, a, b, tr);
         E = 2.0 * (3.0 * tr[0] - 2.0 * tr[1]);
         N = 2.0 * (3.0 * tr[2] - 2.0 * tr[3]);
     }
@@ -343,8 +343,8 @@ int lnv_state_s::step(lnv_result *res)
         st->mul(Y, X, U);
         double tr0[4];
         {
-            const double *a[4] = {X.d(), W.d(), X.d(), W.d()}, *b[4] = {Y.d(), Y.d(), X.d(), X.d()};
-            trace_products(c, 4, X.p, a, X.p, b, tr0);
+            const double *a[2] = {X.d(), W.d()}, *b[2] = {Y.d(), X.d()};   // Tr XY, Tr WY, Tr XX, Tr WX
+            trace_set(c, kTracesEnergy, X.p, a, b, tr0);
         }
         const double E = 2.0 * (3.0 * tr0[0] - 2.0 * tr0[1]);
         const double N = 2.0 * (3.0 * tr0[2] - 2.0 * tr0[3]);
@@ -404,11 +404,11 @@ int lnv_state_s::step(lnv_result *res)
         Mat &M1 = W1;
         double tr[15];
         {
-            const double *a[15] = {XD.d(), X.d(), XD.d(), X.d(), XD.d(), M1.d(), W.d(), Q.d(),
-                                   M1.d(), Q.d(), M1.d(), W.d(), Q.d(), M1.d(), Q.d()};
-            const double *b[15] = {Y.d(), YD.d(), YD.d(), XD.d(), XD.d(), Y.d(), YD.d(), Y.d(),
-                                   YD.d(), YD.d(), X.d(), XD.d(), X.d(), XD.d(), XD.d()};
-            trace_products(c, 15, X.p, a, X.p, b, tr);
+            // Tr of (X_D Y, X Y_D, X_D Y_D, X X_D, X_D X_D, M1 Y, W Y_D, Q Y, M1 Y_D, Q Y_D,
+            //        M1 X, W X_D, Q X, M1 X_D, Q X_D)
+            const double *a[5] = {XD.d(), X.d(), M1.d(), W.d(), Q.d()};
+            const double *b[4] = {Y.d(), YD.d(), XD.d(), X.d()};
+            trace_set(c, kTracesLineSearch, X.p, a, b, tr);
         }
         const double f[4] = {tr0[0], tr[0] + tr[1], tr[2], 0.0};
         const double h[4] = {tr0[2], 2.0 * tr[3], tr[4], 0.0};

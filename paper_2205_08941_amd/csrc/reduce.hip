@@ -53,9 +53,11 @@ __device__ inline int find_in_row(const int *__restrict__ rowptr, const int *__r
 
 // Tr(A_n B_n) = sum over slots s = (i,k) of A of sum_pq A_n[s][p][q] B_n[t][q][p],
 // t = slot of (k, i) in B's pattern (-1: block absent, contributes zero).
-template <int CNT>
+// BC > 0: the block size as a compile-time constant (no integer divisions by a
+// runtime value in the element loop); 0: b from the argument.
+template <int CNT, int BC>
 __global__ __launch_bounds__(kThreads) void k_trace_products(
-    int count, int b, int64_t nnzA, const int *__restrict__ colsA, const int *__restrict__ rowsA,
+    int count, int b_arg, int64_t nnzA, const int *__restrict__ colsA, const int *__restrict__ rowsA,
     const int *__restrict__ tmapA, int same_pattern, const int *__restrict__ rpB,
     const int *__restrict__ colsB, Ptrs A, Ptrs Bp, double *__restrict__ partials)
 {
@@ -63,6 +65,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_products(
     double acc[CNT];
 #pragma unroll
     for (int n = 0; n < CNT; ++n) acc[n] = 0.0;
+    const int b = BC > 0 ? BC : b_arg;
     const int bb = b * b;
     const int64_t nchunks = (nnzA + kChunk - 1) / kChunk;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
@@ -88,6 +91,56 @@ __global__ __launch_bounds__(kThreads) void k_trace_products(
         }
     }
     block_reduce_store<CNT>(acc, count, partials);
+}
+
+// Fixed sets of traces Tr(A_{ai[n]} B_{bi[n]}) over few distinct matrices on
+// one pattern: each element of each distinct matrix is loaded once and used by
+// every trace that needs it.  Per trace the terms are summed in the same order
+// as k_trace_products, so the results are the same bits.
+struct EnergyTraces {   // Tr XY, Tr WY, Tr XX, Tr WX from A = {X, W}, B = {Y, X}
+    static constexpr int na = 2, nb = 2, count = 4;
+    static constexpr int ai[count] = {0, 1, 0, 1}, bi[count] = {0, 0, 1, 1};
+};
+struct LineSearchTraces {   // A = {X_D, X, M1, W, Q}, B = {Y, Y_D, X_D, X}
+    static constexpr int na = 5, nb = 4, count = 15;
+    static constexpr int ai[count] = {0, 1, 0, 1, 0, 2, 3, 4, 2, 4, 2, 3, 4, 2, 4};
+    static constexpr int bi[count] = {0, 1, 1, 2, 2, 0, 1, 0, 1, 1, 3, 2, 3, 2, 2};
+};
+
+template <class TS, int CNT, int BC>
+__global__ __launch_bounds__(kThreads) void k_trace_set(int b_arg, int64_t nnz, const int *__restrict__ tmap,
+                                                        Ptrs A, Ptrs Bp, double *__restrict__ partials)
+{
+    static_assert(TS::count <= CNT, "trace count");
+    __shared__ int tslot[kChunk];
+    double acc[CNT];
+#pragma unroll
+    for (int n = 0; n < CNT; ++n) acc[n] = 0.0;
+    const int b = BC > 0 ? BC : b_arg;
+    const int bb = b * b;
+    const int64_t nchunks = (nnz + kChunk - 1) / kChunk;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t base = ch * kChunk;
+        const int nsl = (int)min((int64_t)kChunk, nnz - base);
+        __syncthreads();
+        if (threadIdx.x < nsl) tslot[threadIdx.x] = tmap[base + threadIdx.x];
+        __syncthreads();
+        const int nel = nsl * bb;
+        for (int e = threadIdx.x; e < nel; e += kThreads) {
+            const int ls = e / bb, r = e - ls * bb;
+            const int p = r / b, q = r - p * b;
+            const int64_t ia = (base + ls) * bb + r;
+            const int64_t ib = (int64_t)tslot[ls] * bb + q * b + p;
+            double av[TS::na], bv[TS::nb];
+#pragma unroll
+            for (int j = 0; j < TS::na; ++j) av[j] = A.p[j][ia];
+#pragma unroll
+            for (int j = 0; j < TS::nb; ++j) bv[j] = Bp.p[j][ib];
+#pragma unroll
+            for (int n = 0; n < TS::count; ++n) acc[n] = fma(av[TS::ai[n]], bv[TS::bi[n]], acc[n]);
+        }
+    }
+    block_reduce_store<CNT>(acc, TS::count, partials);
 }
 
 template <int CNT>
@@ -214,15 +267,55 @@ void trace_products(Context *ctx, int count, const bsm_pattern_s *PA, const doub
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, kRedBlocks));
     const int same = (PA == PB) ? 1 : 0;
     hipStream_t st = ctx->stream;
-#define LAUNCH(C)                                                                                    \
-    k_trace_products<C><<<grid, kThreads, 0, st>>>(count, PA->b, PA->nnzb, PA->cols.as<int>(),        \
-                                                   PA->rowidx.as<int>(), PA->tmap.as<int>(), same,   \
-                                                   PB->rowptr.as<int>(), PB->cols.as<int>(), pa, pb, \
-                                                   ctx->red_partials.as<double>())
+#define LAUNCH_B(C, BC)                                                                                 \
+    k_trace_products<C, BC><<<grid, kThreads, 0, st>>>(count, PA->b, PA->nnzb, PA->cols.as<int>(),        \
+                                                       PA->rowidx.as<int>(), PA->tmap.as<int>(), same,   \
+                                                       PB->rowptr.as<int>(), PB->cols.as<int>(), pa, pb, \
+                                                       ctx->red_partials.as<double>())
+#define LAUNCH(C)                             \
+    do {                                      \
+        if (PA->b == 9) LAUNCH_B(C, 9);       \
+        else if (PA->b == 4) LAUNCH_B(C, 4);  \
+        else LAUNCH_B(C, 0);                  \
+    } while (0)
     if (count == 1) LAUNCH(1);
     else if (count <= 4) LAUNCH(4);
     else LAUNCH(kRedSlots);
 #undef LAUNCH
+#undef LAUNCH_B
+    BSM_HIP_TRY(hipGetLastError());
+    finish(ctx, count, grid, out);
+}
+
+void trace_set(Context *ctx, int kind, const bsm_pattern_s *P, const double *const *A, const double *const *B,
+               double *out)
+{
+    BSM_REQUIRE(kind == kTracesEnergy || kind == kTracesLineSearch, BSM_EINVAL, "bad trace set");
+    Ptrs pa{}, pb{};
+    const int na = kind == kTracesEnergy ? EnergyTraces::na : LineSearchTraces::na;
+    const int nb = kind == kTracesEnergy ? EnergyTraces::nb : LineSearchTraces::nb;
+    const int count = kind == kTracesEnergy ? EnergyTraces::count : LineSearchTraces::count;
+    for (int j = 0; j < na; ++j) pa.p[j] = A[j];
+    for (int j = 0; j < nb; ++j) pb.p[j] = B[j];
+    const int64_t nchunks = (P->nnzb + kChunk - 1) / kChunk;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, kRedBlocks));
+    hipStream_t st = ctx->stream;
+    // the same accumulator widths as trace_products uses for these counts
+    auto go = [&](auto ts, auto cnt) {
+        using TS = decltype(ts);
+        constexpr int C = decltype(cnt)::value;
+        if (P->b == 9)
+            k_trace_set<TS, C, 9><<<grid, kThreads, 0, st>>>(P->b, P->nnzb, P->tmap.as<int>(), pa, pb,
+                                                              ctx->red_partials.as<double>());
+        else if (P->b == 4)
+            k_trace_set<TS, C, 4><<<grid, kThreads, 0, st>>>(P->b, P->nnzb, P->tmap.as<int>(), pa, pb,
+                                                              ctx->red_partials.as<double>());
+        else
+            k_trace_set<TS, C, 0><<<grid, kThreads, 0, st>>>(P->b, P->nnzb, P->tmap.as<int>(), pa, pb,
+                                                              ctx->red_partials.as<double>());
+    };
+    if (kind == kTracesEnergy) go(EnergyTraces{}, std::integral_constant<int, 4>{});
+    else go(LineSearchTraces{}, std::integral_constant<int, kRedSlots>{});
     BSM_HIP_TRY(hipGetLastError());
     finish(ctx, count, grid, out);
 }
