@@ -160,17 +160,6 @@ __global__ __launch_bounds__(64) void k_product_mfma_bf16(
 }
 
 // ---------------------------------------------------------------- planner
-__device__ inline int find_in_row(const int *__restrict__ rp, const int *__restrict__ cols, int i, int j)
-{
-    int lo = rp[i], hi = rp[i + 1], end = hi;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (cols[mid] < j) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < end && cols[lo] == j) ? lo : -1;
-}
-
 // One thread per row group: size of the union of the group's rows of P_C.
 __global__ void k_group_union(int n, int G, const int *__restrict__ rpC, const int *__restrict__ cC,
                               int jt, int *__restrict__ ntile)
@@ -203,12 +192,12 @@ __global__ void k_group_union(int n, int G, const int *__restrict__ rpC, const i
 // column (order 1: row sets in descending bit order, ascending columns inside a
 // set).  With order 1 a tile's columns share their output rows, so a row
 // multiplies in a tile only where it has outputs; the two orders give the same
-// products.  cbuf / mbuf: two ping-pong halves of 2 * ntiles * jt ints each
-// (column, row set), used by order 1 only.
+// products.  scr (order 1 only): per plan 5 + G arrays of ntiles * jt ints, each
+// group using its tiles' range: union columns, row sets and union positions in
+// ping-pong pairs, and the C slots of every (column, row) found by the merge.
 __global__ void k_group_tiles(int n, int G, int jt, int order, const int *__restrict__ rpC,
                               const int *__restrict__ cC, const int64_t *__restrict__ toff, int64_t ntiles,
-                              int *__restrict__ hdr, int *__restrict__ tcols, int *__restrict__ cbuf,
-                              int *__restrict__ mbuf)
+                              int *__restrict__ hdr, int *__restrict__ tcols, int *__restrict__ scr)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int ng = (n + G - 1) / G;
@@ -250,9 +239,12 @@ __global__ void k_group_tiles(int n, int G, int jt, int order, const int *__rest
         }
         return;
     }
-    // order 1: union with row sets, then a stable radix sort on the row-set bits
-    // (least significant first, rows present before rows absent at each bit)
-    int *c0 = cbuf + t0 * jt, *m0 = mbuf + t0 * jt, *c1 = c0 + cap, *m1 = m0 + cap;
+    // order 1: union with row sets and slots, then a stable radix sort of the
+    // union positions on the row-set bits (least significant first, rows present
+    // before rows absent at each bit)
+    const int64_t o = t0 * jt;
+    int *col = scr + o, *m0 = scr + cap + o, *m1 = scr + 2 * cap + o, *x0 = scr + 3 * cap + o,
+        *x1 = scr + 4 * cap + o, *sl = scr + 5 * cap + o * G;
     int cnt = 0;
     while (true) {
         int m = 0x7fffffff;
@@ -260,41 +252,45 @@ __global__ void k_group_tiles(int n, int G, int jt, int order, const int *__rest
             if (p[a] < pe[a]) m = min(m, cC[p[a]]);
         if (m == 0x7fffffff) break;
         int set = 0;
-        for (int a = 0; a < gr; ++a)
-            if (p[a] < pe[a] && cC[p[a]] == m) {
+        for (int a = 0; a < G; ++a) {
+            int slot = -1;
+            if (a < gr && p[a] < pe[a] && cC[p[a]] == m) {
                 set |= 1 << a;
-                ++p[a];
+                slot = p[a]++;
             }
-        c0[cnt] = m;
+            sl[(int64_t)cnt * G + a] = slot;
+        }
+        col[cnt] = m;
         m0[cnt] = set;
+        x0[cnt] = cnt;
         ++cnt;
     }
     for (int bit = 0; bit < gr; ++bit) {
         int w = 0;
         for (int x = 0; x < cnt; ++x)
             if ((m0[x] >> bit) & 1) {
-                c1[w] = c0[x];
-                m1[w++] = m0[x];
+                m1[w] = m0[x];
+                x1[w++] = x0[x];
             }
         for (int x = 0; x < cnt; ++x)
             if (!((m0[x] >> bit) & 1)) {
-                c1[w] = c0[x];
-                m1[w++] = m0[x];
+                m1[w] = m0[x];
+                x1[w++] = x0[x];
             }
-        int *tc = c0, *tm = m0;
-        c0 = c1;
+        int *tm = m0, *tx = x0;
         m0 = m1;
-        c1 = tc;
+        x0 = x1;
         m1 = tm;
+        x1 = tx;
     }
     for (int x = 0; x < cnt; ++x) {
         const int64_t t = t0 + x / jt;
         const int q = x % jt;
         if (q == 0) open_tile(t);
         int *h = hdr + t * hs;
-        tcols[t * jt + q] = c0[x];
-        for (int a = 0; a < gr; ++a)
-            if ((m0[x] >> a) & 1) h[G + a * jt + q] = find_in_row(rpC, cC, i0 + a, c0[x]);
+        const int u = x0[x];
+        tcols[t * jt + q] = col[u];
+        for (int a = 0; a < gr; ++a) h[G + a * jt + q] = sl[(int64_t)u * G + a];
     }
 }
 
@@ -635,11 +631,11 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
     DevBuf tcols(ctx, sizeof(int) * (size_t)std::max<int64_t>(1, nt * jt));
     {
         const int order = ctx->column_order;
-        const size_t sortn = order == 1 ? (size_t)std::max<int64_t>(1, 2 * nt * jt) : 1;
-        DevBuf cbuf(ctx, sizeof(int) * sortn), mbuf(ctx, sizeof(int) * sortn);
+        const size_t scrn = order == 1 ? (size_t)std::max<int64_t>(1, (5 + G) * nt * jt) : 1;
+        DevBuf scr(ctx, sizeof(int) * scrn);
         k_group_tiles<<<(ng + 127) / 128, 128, 0, st>>>(n, G, jt, order, PC->rowptr.as<int>(), PC->cols.as<int>(),
                                                         toff.as<int64_t>(), nt, plan->hdr.as<int>(),
-                                                        tcols.as<int>(), cbuf.as<int>(), mbuf.as<int>());
+                                                        tcols.as<int>(), scr.as<int>());
         BSM_HIP_TRY(hipStreamSynchronize(st));   // before the sort buffers are freed
     }
     DevBuf nent(ctx, sizeof(int64_t) * (size_t)std::max<int64_t>(1, nt)), tri(ctx, 2 * sizeof(unsigned long long));
