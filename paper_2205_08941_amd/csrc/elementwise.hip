@@ -17,14 +17,32 @@ __global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, doubl
     y[e] = (b == 0.0) ? a * x[e] : a * x[e] + b * y[e];
 }
 
-// z <- a x + b y + c z, one element per thread (x or y may be z)
+// z <- a x + b y + c z, one element per thread (x or y may be z).  Each element
+// is fma(c, z, fma(a, x, b y)), written out so that the paired kernel below
+// gives the same bits.
 __global__ void k_axpbypcz(int64_t n, double a, const double *x, double b, const double *y, double c,
                            double *z)
 {
     int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (e >= n) return;
-    double v = a * x[e] + b * y[e];
-    z[e] = (c == 0.0) ? v : v + c * z[e];
+    const double v = fma(a, x[e], b * y[e]);
+    z[e] = (c == 0.0) ? v : fma(c, z[e], v);
+}
+
+// The same for an even count of 16-byte aligned elements, two per thread
+// (16-byte loads and stores).
+__global__ void k_axpbypcz2(int64_t n2, double a, const double2 *x, double b, const double2 *y, double c,
+                            double2 *z)
+{
+    int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= n2) return;
+    const double2 xv = x[e], yv = y[e];
+    double2 v = make_double2(fma(a, xv.x, b * yv.x), fma(a, xv.y, b * yv.y));
+    if (c != 0.0) {
+        const double2 zv = z[e];
+        v = make_double2(fma(c, zv.x, v.x), fma(c, zv.y, v.y));
+    }
+    z[e] = v;
 }
 
 // In place (M_ij, M_ji) <- ((M_ij + M_ji^T)/2, its transpose).  The thread of
@@ -139,7 +157,14 @@ void axpbypcz(Context *ctx, int64_t n, double a, const double *x, double b, cons
               double *z)
 {
     if (n <= 0) return;
-    k_axpbypcz<<<grid1(n), kT, 0, ctx->stream>>>(n, a, x, b, y, c, z);
+    const bool paired = (n % 2 == 0) && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) |
+                                          reinterpret_cast<uintptr_t>(z)) % 16 == 0);
+    if (paired)
+        k_axpbypcz2<<<grid1(n / 2), kT, 0, ctx->stream>>>(n / 2, a, reinterpret_cast<const double2 *>(x), b,
+                                                          reinterpret_cast<const double2 *>(y), c,
+                                                          reinterpret_cast<double2 *>(z));
+    else
+        k_axpbypcz<<<grid1(n), kT, 0, ctx->stream>>>(n, a, x, b, y, c, z);
     BSM_HIP_TRY(hipGetLastError());
 }
 
