@@ -167,9 +167,9 @@ int bsm_ctx_set_column_order(bsm_ctx ctx, int order);
  * planned as C = (B^T A^T)^T, i.e. D = B^T A^T on P_C with blocks read transposed
  * and D's blocks stored transposed at the slots of (j, i) (patterns are
  * symmetric).  A wide A times a narrow B then walks the narrow pattern, leaving
- * fewer lanes idle.  mode 0: never; 1 (default): the plan with the smaller
- * estimated cost (rows multiplied + 4.5 x entries) is kept; 2: always when
- * eligible.  Each element sums the same terms in the same order either way, so
+ * fewer lanes idle.  mode 0: never; 1 (default): both plans are built once and
+ * the one with the smaller estimated cost (rows multiplied + 4.5 x entries) is
+ * kept; 2: always when eligible.  Each element sums the same terms in the same order either way, so
  * results are equal.  BF16 products on the matrix cores always use direct plans.
  * Clears cached plans (destroy batches first). */
 int bsm_ctx_set_transposed_plans(bsm_ctx ctx, int mode);
