@@ -319,6 +319,27 @@ def test_transposed_plans_agree(bsm, b, rows):
                 assert rel_err(out[mode, n, prec], Co.blocks) < tol, (mode, ra, rb, rc, prec)
 
 
+@pytest.mark.parametrize("b", [4, 9])
+def test_transposed_plan_beta_zero_ignores_nan(bsm, b):
+    """A transposed plan with beta = 0 writes every C block (at the transposed slots)
+    without reading C: a NaN-filled C comes out finite and equal to the direct plan's."""
+    s = SYSTEMS["si216_disp"]()
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
+    a = synth.random_blocks(op[14].nnz, b, 180)
+    bb = synth.random_blocks(op[6].nnz, b, 181)
+    out = {}
+    for mode in (0, 2):
+        ctx = bsm.Context(0)
+        ctx.set_transposed_plans(mode)
+        gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
+        C = gmat(bsm, gp[8], np.full((op[8].nnz, b, b), np.nan))
+        bsm.multiply_truncate(1.0, gmat(bsm, gp[14], a), gmat(bsm, gp[6], bb), 0.0, C)
+        out[mode] = host(C)
+        ctx.close()
+    assert np.isfinite(out[2]).all()
+    assert np.array_equal(out[0], out[2])
+
+
 def test_transposed_plans_reject_bad_mode(bsm, ctx):
     with pytest.raises(bsm.BSMError):
         ctx.set_transposed_plans(3)
