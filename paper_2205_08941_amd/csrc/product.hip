@@ -36,6 +36,7 @@ namespace {
 constexpr int kXcd = 8;       // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int kWaves = 4;     // wavefronts (tiles) per workgroup
 constexpr int kMaxRows = 16;  // rows of a tile, at most
+constexpr int kPlanChunks = 4;   // planner threads per tile (chunks of the k range)
 
 __device__ inline int64_t logical_workgroup(int64_t nwg_padded)
 {
@@ -294,13 +295,17 @@ __global__ void k_group_tiles(int n, int G, int jt, int order, const int *__rest
     }
 }
 
-// One thread per tile: walk the union over the group's rows of P_A (k ascending);
-// keep k when some (i_a, k, j) triple exists.  MODE 0 counts entries and triples,
-// MODE 1 writes the entries.  W = 2 (tiles shared by two waves): each entry is two
+// One thread per (tile, chunk of k): walk the union over the tile's rows of P_A
+// (k ascending) for k in [c n / nch, (c + 1) n / nch); keep k when some
+// (i_a, k, j) triple exists.  MODE 0 counts entries and triples per (tile,
+// chunk), MODE 1 writes the entries; a tile's chunks follow each other, so its
+// entries stay in ascending k.  The tile's last chunk writes the padding entry
+// that makes the tile's count even (its count includes it, k_pad_counts).  W = 2 (tiles shared by two waves): each entry is two
 // halves, one per wave and its jt / 2 columns, each with the A slots of the rows
 // that have a live triple in those columns and then those columns' B slots.
 template <int MODE>
-__global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, int tr, const int *__restrict__ hdr,
+__global__ void k_tile_entries(int64_t ntiles, int nch, int natoms, int G, int jt, int W, int tr,
+                               const int *__restrict__ hdr,
                                const int *__restrict__ tcols, const int *__restrict__ rpA,
                                const int *__restrict__ cA, const int *__restrict__ tmA,
                                const int *__restrict__ rpB, const int *__restrict__ cB,
@@ -308,23 +313,35 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, int tr, con
                                unsigned long long *__restrict__ triples, unsigned long long *__restrict__ rowwork,
                                const int64_t *__restrict__ ebeg, int *__restrict__ ent)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
+    const int64_t tc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tc >= ntiles * nch) return;
+    const int64_t t = tc / nch;
+    const int c = (int)(tc - t * nch);
+    const int k0 = (int)((int64_t)c * natoms / nch), k1 = (int)((int64_t)(c + 1) * natoms / nch);
     const int hs = G + G * jt, es = W * G + jt, jh = jt / W;
     const int *h = hdr + t * hs;
     int pa[kMaxRows], pae[kMaxRows], pb[64], pbe[64], jcol[64];
+    // first position in cols[lo, hi) at or past value v
+    auto lower = [](const int *__restrict__ cols, int lo, int hi, int v) {
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cols[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
     for (int a = 0; a < G; ++a) {
         const int i = h[a];
-        pa[a] = (i >= 0) ? rpA[i] : 0;
-        pae[a] = (i >= 0) ? rpA[i + 1] : 0;
+        pa[a] = (i >= 0) ? lower(cA, rpA[i], rpA[i + 1], k0) : 0;
+        pae[a] = (i >= 0) ? lower(cA, pa[a], rpA[i + 1], k1) : 0;
     }
     for (int x = 0; x < jt; ++x) {
         const int j = tcols[t * jt + x];
         jcol[x] = j;
-        pb[x] = (j >= 0) ? rpB[j] : 0;
-        pbe[x] = (j >= 0) ? rpB[j + 1] : 0;
+        pb[x] = (j >= 0) ? lower(cB, rpB[j], rpB[j + 1], k0) : 0;
+        pbe[x] = (j >= 0) ? lower(cB, pb[x], rpB[j + 1], k1) : 0;
     }
-    int64_t w = (MODE == 1) ? ebeg[t] : 0;
+    int64_t w = (MODE == 1) ? ebeg[tc] : 0;
     int64_t cnt = 0;
     unsigned long long tri = 0, rw = 0;
     while (true) {
@@ -375,18 +392,34 @@ __global__ void k_tile_entries(int64_t ntiles, int G, int jt, int W, int tr, con
         tri += ntri;
         for (int hf = 0; hf < W; ++hf) rw += __popc(rowlive[hf]);   // rows multiplied
     }
-    if (cnt & 1) {   // pad to an even count with an entry that multiplies nothing
-        if (MODE == 1) {
-            int *e = ent + w * es;
-            for (int x = 0; x < es; ++x) e[x] = -1;
-        }
-        ++cnt;
+    if (MODE == 1 && c == nch - 1 && w < ebeg[tc + 1]) {   // the padding entry: multiplies nothing
+        int *e = ent + w * es;
+        for (int x = 0; x < es; ++x) e[x] = -1;
     }
     if (MODE == 0) {
-        nent[t] = cnt;
+        nent[tc] = cnt;
         atomicAdd(triples, tri);   // integers: order-independent
         atomicAdd(rowwork, rw);
     }
+}
+
+// One thread per tile: make the tile's entry count even by counting a padding
+// entry in its last chunk.
+__global__ void k_pad_counts(int64_t ntiles, int nch, int64_t *__restrict__ nent)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int64_t sum = 0;
+    for (int c = 0; c < nch; ++c) sum += nent[t * nch + c];
+    if (sum & 1) nent[t * nch + nch - 1] += 1;
+}
+
+// One thread per tile: the tile's entry range from the (tile, chunk) ranges.
+__global__ void k_tile_ebeg(int64_t ntiles, int nch, const int64_t *__restrict__ ebeg_tc, int64_t *__restrict__ ebeg)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    ebeg[t] = ebeg_tc[t * nch];
 }
 
 // One thread per tile of a transposed plan: C slots of (i, j) -> slots of (j, i).
@@ -638,31 +671,38 @@ void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, 
                                                         tcols.as<int>(), scr.as<int>());
         BSM_HIP_TRY(hipStreamSynchronize(st));   // before the sort buffers are freed
     }
-    DevBuf nent(ctx, sizeof(int64_t) * (size_t)std::max<int64_t>(1, nt)), tri(ctx, 2 * sizeof(unsigned long long));
+    // entries are planned per (tile, chunk of k) for parallelism; kPlanChunks chunks per tile
+    const int nch = kPlanChunks;
+    const int64_t ntc = nt * nch;
+    DevBuf nent(ctx, sizeof(int64_t) * (size_t)std::max<int64_t>(1, ntc)), tri(ctx, 2 * sizeof(unsigned long long));
+    DevBuf ebeg_tc(ctx, sizeof(int64_t) * (size_t)(ntc + 1));
     plan->ebeg = DevBuf(ctx, sizeof(int64_t) * (size_t)(nt + 1));
     BSM_HIP_TRY(hipMemsetAsync(tri.ptr, 0, 2 * sizeof(unsigned long long), st));
     BSM_HIP_TRY(hipMemsetAsync(plan->ebeg.ptr, 0, sizeof(int64_t) * (size_t)(nt + 1), st));
     int64_t ne = 0;
     unsigned long long ntri[2] = {0, 0};   // triples, rows multiplied
     if (nt > 0) {
-        const unsigned grid = (unsigned)((nt + 127) / 128);
-        k_tile_entries<0><<<grid, 128, 0, st>>>(nt, G, jt, waves, transposed, plan->hdr.as<int>(), tcols.as<int>(),
-                                                PA->rowptr.as<int>(), PA->cols.as<int>(), PA->tmap.as<int>(),
-                                                PB->rowptr.as<int>(), PB->cols.as<int>(),
+        const unsigned grid = (unsigned)((ntc + 127) / 128);
+        k_tile_entries<0><<<grid, 128, 0, st>>>(nt, nch, PA->natoms, G, jt, waves, transposed, plan->hdr.as<int>(),
+                                                tcols.as<int>(), PA->rowptr.as<int>(), PA->cols.as<int>(),
+                                                PA->tmap.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
                                                 PB->tmap.as<int>(), nent.as<int64_t>(),
                                                 tri.as<unsigned long long>(), tri.as<unsigned long long>() + 1,
                                                 nullptr, nullptr);
-        k_scan64<<<1, 1024, 0, st>>>(nt, nent.as<int64_t>(), plan->ebeg.as<int64_t>());
-        BSM_HIP_TRY(hipMemcpyAsync(&ne, plan->ebeg.as<int64_t>() + nt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        k_pad_counts<<<(unsigned)((nt + 127) / 128), 128, 0, st>>>(nt, nch, nent.as<int64_t>());
+        k_scan64<<<1, 1024, 0, st>>>(ntc, nent.as<int64_t>(), ebeg_tc.as<int64_t>());
+        k_tile_ebeg<<<(unsigned)((nt + 1 + 127) / 128), 128, 0, st>>>(nt, nch, ebeg_tc.as<int64_t>(),
+                                                                      plan->ebeg.as<int64_t>());
+        BSM_HIP_TRY(hipMemcpyAsync(&ne, ebeg_tc.as<int64_t>() + ntc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         BSM_HIP_TRY(hipMemcpyAsync(ntri, tri.ptr, sizeof(ntri), hipMemcpyDeviceToHost, st));
         BSM_HIP_TRY(hipStreamSynchronize(st));
         plan->ent = DevBuf(ctx, sizeof(int) * (size_t)((ne + 4) * es));   // 4 spare entries
         BSM_HIP_TRY(hipMemsetAsync(plan->ent.as<int>() + ne * es, 0xff, sizeof(int) * 4 * es, st));
-        k_tile_entries<1><<<grid, 128, 0, st>>>(nt, G, jt, waves, transposed, plan->hdr.as<int>(), tcols.as<int>(),
-                                                PA->rowptr.as<int>(), PA->cols.as<int>(), PA->tmap.as<int>(),
-                                                PB->rowptr.as<int>(), PB->cols.as<int>(),
-                                                PB->tmap.as<int>(), nullptr, nullptr, nullptr, plan->ebeg.as<int64_t>(),
-                                                plan->ent.as<int>());
+        k_tile_entries<1><<<grid, 128, 0, st>>>(nt, nch, PA->natoms, G, jt, waves, transposed, plan->hdr.as<int>(),
+                                                tcols.as<int>(), PA->rowptr.as<int>(), PA->cols.as<int>(),
+                                                PA->tmap.as<int>(), PB->rowptr.as<int>(), PB->cols.as<int>(),
+                                                PB->tmap.as<int>(), nullptr, nullptr, nullptr,
+                                                ebeg_tc.as<int64_t>(), plan->ent.as<int>());
         BSM_HIP_TRY(hipGetLastError());
     } else {
         plan->ent = DevBuf(ctx, sizeof(int) * 4 * es);

@@ -40,9 +40,10 @@ static HostPattern load(const char *fn)
 
 int main(int argc, char **argv)
 {
-    if (argc != 9) return 2;
+    if (argc != 10) return 2;
     const HostPattern A = load(argv[1]), Bp = load(argv[2]), C = load(argv[3]);
     const int G = atoi(argv[4]), JT = atoi(argv[5]), W = atoi(argv[6]), order = atoi(argv[7]), tr = atoi(argv[8]);
+    const int nch = atoi(argv[9]);   // planner threads per tile
     const int n = C.n, jt = JT * W;
     const HostPattern &KA = tr ? Bp : A, &KB = tr ? A : Bp;   // the kernel's operands
     const int ng = (n + G - 1) / G;
@@ -63,20 +64,30 @@ int main(int argc, char **argv)
         k_group_tiles(n, G, jt, order, C.rp.data(), C.cc.data(), toff.data(), nt, hdr.data(), tcols.data(),
                       scr.data());
     }
-    std::vector<int64_t> nent(nt), ebeg(nt + 1, 0);
+    const int64_t ntc = nt * nch;
+    std::vector<int64_t> nent(ntc), ebeg_tc(ntc + 1, 0), ebeg(nt + 1, 0);
     unsigned long long tri = 0, rw = 0;
+    for (int64_t tc = 0; tc < ntc; ++tc) {
+        blockIdx.x = (int)tc;
+        k_tile_entries<0>(nt, nch, n, G, jt, W, tr, hdr.data(), tcols.data(), KA.rp.data(), KA.cc.data(),
+                          KA.tm.data(), KB.rp.data(), KB.cc.data(), KB.tm.data(), nent.data(), &tri, &rw, nullptr,
+                          nullptr);
+    }
     for (int64_t t = 0; t < nt; ++t) {
         blockIdx.x = (int)t;
-        k_tile_entries<0>(nt, G, jt, W, tr, hdr.data(), tcols.data(), KA.rp.data(), KA.cc.data(), KA.tm.data(),
-                          KB.rp.data(), KB.cc.data(), KB.tm.data(), nent.data(), &tri, &rw, nullptr, nullptr);
-        ebeg[t + 1] = ebeg[t] + nent[t];
+        k_pad_counts(nt, nch, nent.data());
+    }
+    for (int64_t tc = 0; tc < ntc; ++tc) ebeg_tc[tc + 1] = ebeg_tc[tc] + nent[tc];
+    for (int64_t t = 0; t <= nt; ++t) {
+        blockIdx.x = (int)t;
+        k_tile_ebeg(nt, nch, ebeg_tc.data(), ebeg.data());
     }
     std::vector<int> ent((ebeg[nt] + 4) * es, -7);
-    for (int64_t t = 0; t < nt; ++t) {
-        blockIdx.x = (int)t;
-        k_tile_entries<1>(nt, G, jt, W, tr, hdr.data(), tcols.data(), KA.rp.data(), KA.cc.data(), KA.tm.data(),
-                          KB.rp.data(), KB.cc.data(), KB.tm.data(), nullptr, nullptr, nullptr, ebeg.data(),
-                          ent.data());
+    for (int64_t tc = 0; tc < ntc; ++tc) {
+        blockIdx.x = (int)tc;
+        k_tile_entries<1>(nt, nch, n, G, jt, W, tr, hdr.data(), tcols.data(), KA.rp.data(), KA.cc.data(),
+                          KA.tm.data(), KB.rp.data(), KB.cc.data(), KB.tm.data(), nullptr, nullptr, nullptr,
+                          ebeg_tc.data(), ent.data());
     }
     if (tr)
         for (int64_t t = 0; t < nt; ++t) {
@@ -98,6 +109,29 @@ int main(int argc, char **argv)
             }
     for (int v : owner)
         if (v != 1) ++bad;
+    // entries of a tile in strictly ascending k (padding entries, all slots -1, only at the end)
+    for (int64_t t = 0; t < nt; ++t) {
+        int last = -1;
+        bool padded = false;
+        for (int64_t q = ebeg[t]; q < ebeg[t + 1]; ++q) {
+            int k = -1;
+            for (int hf = 0; hf < W && k < 0; ++hf) {
+                const int *e = &ent[q * es + hf * (G + JT)];
+                for (int a = 0; a < G && k < 0; ++a)
+                    if (e[a] >= 0) {
+                        if (!tr) k = A.cc[e[a]];
+                        else {
+                            int r = 0;
+                            while (!(e[a] >= Bp.rp[r] && e[a] < Bp.rp[r + 1])) ++r;
+                            k = r;
+                        }
+                    }
+            }
+            if (k < 0) { padded = true; continue; }
+            if (padded || k <= last) ++bad;
+            last = k;
+        }
+    }
     // every scheduled triple real, with its A, B and C slots
     unsigned long long seen = 0;
     for (int64_t t = 0; t < nt; ++t) {
