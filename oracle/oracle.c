@@ -19,7 +19,7 @@
  * Storage: block CSR.  rowptr[n+1] (int64), cols[nnz] (int32, ascending within
  * a row), vals[nnz * b * b] (row-major b x b per block, in CSR order).
  *
- * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no FMA contraction,
+ * Build: gcc -O3 -march=native -fopenmp -ffp-contract=off -shared -fPIC (no FMA contraction,
  * so distances are rounded exactly as written).
  */
 #include <math.h>
@@ -124,12 +124,18 @@ void orc_multiply(int n, int b, double alpha,
                     if (t < 0) continue;
                     const double *bk = vB + sb * bb;
                     double *c = acc + t * bb;
-                    for (int p = 0; p < b; ++p)
-                        for (int q = 0; q < b; ++q) {
-                            double sum = 0.0;
-                            for (int m = 0; m < b; ++m) sum += a[p * b + m] * bk[m * b + q];
-                            c[p * b + q] += sum;
+                    /* c[p][q] += sum over m of a[p][m] bk[m][q], each sum
+                       started at zero and taken in ascending m; the q sums of
+                       one p are carried side by side */
+                    for (int p = 0; p < b; ++p) {
+                        double sum[b];
+                        for (int q = 0; q < b; ++q) sum[q] = 0.0;
+                        for (int m = 0; m < b; ++m) {
+                            const double apm = a[p * b + m];
+                            for (int q = 0; q < b; ++q) sum[q] += apm * bk[m * b + q];
                         }
+                        for (int q = 0; q < b; ++q) c[p * b + q] += sum[q];
+                    }
                 }
             }
             for (int64_t s = c0; s < c1; ++s) {

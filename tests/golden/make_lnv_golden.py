@@ -1,0 +1,150 @@
+"""Write the stored oracle values of full Hotelling + LNV solves.
+
+Calls only the FP64 CPU oracle (`oracle`) and the seeded input generator
+(`synth`); nothing here touches the HIP library.  The GPU tests compare the
+library's solve of the same seeded system with these values.
+
+Cases:
+  si4096_b9      4096-atom diamond Si (8x8x8 cells), 9 orbitals per atom,
+                 S/H on 6 A, S^-1 on 8 A, L on 10 A: Hotelling to its floor,
+                 then LNV to |dE| < 1e-8 Ha (hours on a few CPU cores, ~30 GB).
+  si512_b9_disp  512 atoms (4x4x4 cells), Gaussian displacements sigma 0.05 A,
+                 the same cutoffs: the L, S^-1 and S patterns are genuinely
+                 sparse (191, 99 and 47 of 512 columns on the ideal lattice).
+
+Stored per case (JSON): the Hotelling residual after every update, the
+Gershgorin scale and the update count; the initial-guess traces; per LNV
+iteration E, N, mu, alpha, beta, dE and Omega; 64 seeded sample blocks of the
+final S^-1 and L with their (row, column); the Frobenius norm of every block
+row of both; wall times and the thread count of this run.
+
+Usage:  python tests/golden/make_lnv_golden.py si512_b9_disp [si4096_b9 ...]
+"""
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle as O   # noqa: E402
+import synth         # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+HOT_MAX_ITER, HOT_TOL = 100, 1e-12
+TOL_E, MAX_LNV = 1e-8, 300
+SAMPLES = 64
+
+
+def case_system(name):
+    if name == "si4096_b9":
+        return synth.si4096_b9()
+    if name == "si512_b9_disp":
+        return synth.make_system("si512_b9_disp", 4, 9, synth.BIG_CUTOFFS, 7, displacement_sigma=0.05)
+    raise ValueError(name)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def sample_blocks(M, rng):
+    P = M.pattern
+    slots = np.sort(rng.choice(P.nnz, size=min(SAMPLES, P.nnz), replace=False))
+    rows = P.rows()[slots]
+    return {"rows": rows.tolist(), "cols": P.cols[slots].tolist(),
+            "blocks": [[float(v) for v in M.blocks[s].ravel()] for s in slots]}
+
+
+def row_norms(M):
+    P = M.pattern
+    sq = np.einsum("nab,nab->n", M.blocks, M.blocks)
+    per_row = np.add.reduceat(sq, P.rowptr[:-1]) if P.nnz else np.zeros(P.natoms)
+    return [float(math.sqrt(v)) for v in per_row]
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def run(name):
+    s = case_system(name)
+    cut = s.cutoffs
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    log(f"[{name}] {s.natoms} atoms, b={s.b}, cutoffs {cut}, {threads} threads")
+    t_all = time.perf_counter()
+    PS = O.create_pattern(s.positions, s.box, cut["S"])
+    PZ = O.create_pattern(s.positions, s.box, cut["Z"])
+    PL = O.create_pattern(s.positions, s.box, cut["L"])
+    S = O.from_blocks(PS, s.b, s.S.rows, s.S.cols, s.S.blocks)
+    H = O.from_blocks(PS, s.b, s.H.rows, s.H.cols, s.H.blocks)
+
+    t0 = time.perf_counter()
+    hr = O.hotelling_inverse(S, PZ, max_iter=HOT_MAX_ITER, tol=HOT_TOL)
+    hot_s = time.perf_counter() - t0
+    log(f"[{name}] Hotelling: status {hr.status}, {hr.iterations} updates, residuals "
+        f"{hr.residuals[0]:.6e} -> {hr.residuals[-1]:.6e}, {hot_s:.1f} s")
+    if hr.status != O.OK:
+        raise RuntimeError(f"Hotelling failed with status {hr.status}")
+
+    t0 = time.perf_counter()
+    st = O.lnv_init(S, H, hr.Z, PL, s.n_electrons, tol_E=TOL_E)
+    init_s = time.perf_counter() - t0
+    log(f"[{name}] initial L: {init_s:.1f} s")
+    iters, step_s = [], []
+    converged = False
+    for it in range(1, MAX_LNV + 1):
+        t0 = time.perf_counter()
+        r = O.lnv_step(st)
+        step_s.append(time.perf_counter() - t0)
+        if r.status != O.OK:
+            raise RuntimeError(f"LNV step {it} failed with status {r.status}")
+        iters.append({"E": r.E, "N": r.N, "mu": r.mu, "alpha": r.alpha, "beta": r.beta,
+                      "dE": r.dE, "Omega": r.Omega})
+        log(f"[{name}] LNV {it:3d}  E={r.E:.12f}  dE={r.dE:+.3e}  N={r.N:.10f}  mu={r.mu:+.6e}  "
+            f"alpha={r.alpha:.6e}  {step_s[-1]:.1f} s")
+        if r.converged:
+            converged = True
+            break
+    lnv_s = sum(step_s)
+    rng = np.random.default_rng(2205)
+    out = {
+        "case": name,
+        "generator": {"ncell": [int(round(v / synth.A_SI)) for v in s.box], "b": s.b, "cutoffs_A": cut,
+                      "seed": s.seed, "natoms": s.natoms, "n_electrons": s.n_electrons},
+        "hotelling": {"max_iter": HOT_MAX_ITER, "tol": HOT_TOL, "status": hr.status,
+                      "iterations": hr.iterations, "alpha": hr.alpha, "residuals": hr.residuals},
+        "lnv": {"tol_E": TOL_E, "max_iter": MAX_LNV, "converged": converged, "iterations": iters,
+                "E_final": iters[-1]["E"]},
+        "Z_samples": sample_blocks(st.Z, rng),
+        "L_samples": sample_blocks(st.L, rng),
+        "Z_row_norms": row_norms(st.Z),
+        "L_row_norms": row_norms(st.L),
+        "L_norm": float(np.linalg.norm(st.L.blocks.ravel())),
+        "timing": {"threads": threads, "cpu": cpu_model(), "hotelling_s": hot_s, "init_s": init_s,
+                   "lnv_s": lnv_s, "lnv_step_s": step_s, "solve_s": hot_s + init_s + lnv_s,
+                   "total_s": time.perf_counter() - t_all},
+    }
+    path = os.path.join(HERE, f"lnv_{name}.json")
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f, indent=0)
+    os.replace(path + ".tmp", path)
+    log(f"[{name}] wrote {path}: {len(iters)} LNV iterations, E = {iters[-1]['E']:.12f}, "
+        f"solve {hot_s + init_s + lnv_s:.1f} s")
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or ["si512_b9_disp"]:
+        run(name)
