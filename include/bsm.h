@@ -293,6 +293,22 @@ int bsm_product_flops(bsm_ctx ctx, bsm_pattern PA, bsm_pattern PB, bsm_pattern P
  * finite; *out is still written). */
 int bsm_trace_product(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): Tr(A B) as
+ * bsm_trace_product computes it (same kernels and reduction order, so the same
+ * bits), written to out_dev, one double in DEVICE memory, asynchronously on the
+ * context stream.  The per-workgroup partial sums live in a static device array
+ * of the library (1032 doubles = 8256 bytes per GPU, held until the process
+ * ends), whose address bsm_ctx_create takes once per device; the call itself
+ * allocates nothing, copies nothing to the host and does not synchronise, so
+ * it reports no BSM_ENONFINITE (a non-finite trace is written as it is).  The
+ * number of partial sums is fixed by the reduction grid (at most 1024), so no
+ * input size exceeds the scratch.  All calls on one GPU share that array:
+ * calls that overlap in time on one GPU (other streams, other contexts, other
+ * threads) race and give wrong results; calls ordered on one stream are safe.
+ * Errors: BSM_EINVAL (NULL argument, non-FP64 matrix), BSM_EPATTERN, BSM_EHIP. */
+int bsm_trace_product_noalloc(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, double *out_dev);
+
 /* ---- Hotelling iteration for S^-1 (paper: linear-scaling inversion of the
  *      overlap matrix, Development Priorities) ---------------------------- */
 typedef struct {

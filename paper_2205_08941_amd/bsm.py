@@ -150,6 +150,7 @@ EXPORTS = {
                                            ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix)]),
     "bsm_trace_product": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                   ctypes.POINTER(c_double)]),
+    "bsm_trace_product_noalloc": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix), c_void_p]),
     "bsm_batch_create": (c_int, [c_void_p, c_int, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                  ctypes.POINTER(_Matrix), ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                  c_int, ctypes.POINTER(c_void_p)]),
@@ -394,6 +395,15 @@ def trace_product(A: Matrix, B: Matrix) -> float:
     out = c_double()
     _check(_lib.bsm_trace_product(A.pattern.ctx.handle, A.c, B.c, ctypes.byref(out)))
     return out.value
+
+
+def trace_product_noalloc(A: Matrix, B: Matrix, out: torch.Tensor) -> None:
+    """Tr(A B) into out[0] (a float64 tensor on the device), asynchronously, with no
+    allocation in the library (its partial sums sit in a static device array shared by
+    every call on the GPU: overlapping calls race)."""
+    if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 1:
+        raise ValueError("out must be a float64 device tensor with at least one element")
+    _check(_lib.bsm_trace_product_noalloc(A.pattern.ctx.handle, A.c, B.c, c_void_p(out.data_ptr())))
 
 
 def dot(A: Matrix, B: Matrix) -> float:

@@ -191,6 +191,7 @@ int bsm_ctx_create(int device, void *hip_stream, bsm_alloc_fn alloc, bsm_free_fn
     c->c.zero_block = DevBuf(&c->c, sizeof(double) * 256);
     BSM_HIP_TRY(hipMemset(c->c.zero_block.ptr, 0, sizeof(double) * 256));
     BSM_HIP_TRY(hipHostMalloc((void **)&c->c.host_scalars, sizeof(double) * 64, hipHostMallocDefault));
+    trace_scratch_setup(device);   // the allocation-free trace's scratch on this device
     *out = c.release();
     return BSM_OK;
     BSM_API_END
@@ -523,6 +524,19 @@ int bsm_trace_product(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, dou
     const double *a = (const double *)A->blocks, *b = (const double *)B->blocks;
     trace_products(&ctx->c, 1, A->pattern, &a, B->pattern, &b, out);
     if (!std::isfinite(*out)) return fail(BSM_ENONFINITE, "trace is not finite");
+    return BSM_OK;
+    BSM_API_END
+}
+
+int bsm_trace_product_noalloc(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, double *out_dev)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr && out_dev != nullptr, BSM_EINVAL, "NULL argument");
+    check_matrix(A, "A");
+    check_matrix(B, "B");
+    check_same_shape(A, B);
+    trace_product_noalloc(&ctx->c, A->pattern, (const double *)A->blocks, B->pattern, (const double *)B->blocks,
+                          out_dev);
     return BSM_OK;
     BSM_API_END
 }

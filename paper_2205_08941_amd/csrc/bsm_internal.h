@@ -202,6 +202,13 @@ void trace_set(Context *ctx, int kind, const bsm_pattern_s *P, const double *con
 void dots(Context *ctx, int count, const bsm_pattern_s *P, const double *const *A,
           const double *const *B, double *out);
 double trace_single(Context *ctx, const bsm_pattern_s *P, const double *A);
+// Address of the allocation-free trace's static scratch on `device` (the current
+// device), taken once per device; called by bsm_ctx_create.
+void trace_scratch_setup(int device);
+// Tr(A B) into *out_dev (device memory), asynchronous, partial sums in the static
+// scratch: no allocation and no synchronisation.
+void trace_product_noalloc(Context *ctx, const bsm_pattern_s *PA, const double *A, const bsm_pattern_s *PB,
+                           const double *B, double *out_dev);
 double max_abs_row_sum(Context *ctx, const bsm_pattern_s *P, const double *A);
 // ||A - I||_F^2, elementwise.  Synchronises.
 double dist_identity_sq(Context *ctx, const bsm_pattern_s *P, const double *A);

@@ -11,6 +11,7 @@
 #include "bsm_internal.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace bsm {
 namespace {
@@ -198,8 +199,8 @@ __global__ __launch_bounds__(kThreads) void k_dist_identity(int64_t nnz, int b, 
 }
 
 // Partial sums of every slot n added in workgroup order (one workgroup).
-__global__ __launch_bounds__(kThreads) void k_finish(int count, int nparts, const double *__restrict__ partials,
-                                                     double *__restrict__ out)
+__device__ inline void k_finish_body(int count, int nparts, const double *__restrict__ partials,
+                                     double *__restrict__ out)
 {
     __shared__ double red[kThreads];
     for (int n = 0; n < count; ++n) {
@@ -216,6 +217,12 @@ __global__ __launch_bounds__(kThreads) void k_finish(int count, int nparts, cons
         if (threadIdx.x == 0) out[n] = red[0];
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_finish(int count, int nparts, const double *__restrict__ partials,
+                                                     double *__restrict__ out)
+{
+    k_finish_body(count, nparts, partials, out);
 }
 
 // Largest absolute row sum (max over scalar rows of sum_j |A_ij|); max is
@@ -254,6 +261,27 @@ void finish(Context *ctx, int count, int nparts, double *out)
 
 }  // namespace
 
+// ---------------------------------------------------------------- allocation-free trace
+// Scratch of bsm_trace_product_noalloc: the per-workgroup partial sums of one
+// trace (at most kRedBlocks of them, whatever the input size), then the result
+// slot the final pass writes before it is copied to the caller's pointer.
+// Each GPU the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address taken by trace_scratch_setup.
+constexpr int kTraceScratchDoubles = kRedBlocks + 8;
+static __device__ __align__(256) double scratch[kTraceScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double *g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, once taken
+
+// Result of the allocation-free trace: *out = partial sums' total (one workgroup,
+// the same fixed order as the general final pass).
+__global__ __launch_bounds__(kThreads) void k_finish_to(int nparts, const double *__restrict__ partials,
+                                                        double *__restrict__ out)
+{
+    k_finish_body(1, nparts, partials, out);
+}
+
 void trace_products(Context *ctx, int count, const bsm_pattern_s *PA, const double *const *A,
                     const bsm_pattern_s *PB, const double *const *B, double *out)
 {
@@ -285,6 +313,52 @@ void trace_products(Context *ctx, int count, const bsm_pattern_s *PA, const doub
 #undef LAUNCH_B
     BSM_HIP_TRY(hipGetLastError());
     finish(ctx, count, grid, out);
+}
+
+// Take the device address of `scratch` on `device` (current), once per device.
+void trace_scratch_setup(int device)
+{
+    BSM_REQUIRE(device >= 0 && device < kMaxDevices, BSM_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return;
+    void *ptr = nullptr;
+    BSM_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    BSM_REQUIRE(ptr != nullptr, BSM_EHIP, "no device address for the trace scratch");
+    g_scratch_ptr[device] = (double *)ptr;
+}
+
+// Tr(A B) into a device double, asynchronously on the context stream, with the
+// partial sums in `scratch`: no allocation, no synchronisation.  Same kernels,
+// grid and order as trace_products with one trace, so the same bits.
+void trace_product_noalloc(Context *ctx, const bsm_pattern_s *PA, const double *A, const bsm_pattern_s *PB,
+                           const double *B, double *out_dev)
+{
+    double *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (ctx->device >= 0 && ctx->device < kMaxDevices) ptr = g_scratch_ptr[ctx->device];
+    }
+    BSM_REQUIRE(ptr != nullptr, BSM_EHIP, "trace scratch address not taken for this device");
+    Ptrs pa{}, pb{};
+    pa.p[0] = A;
+    pb.p[0] = B;
+    const int64_t nchunks = (PA->nnzb + kChunk - 1) / kChunk;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nchunks, kRedBlocks));
+    static_assert(kRedBlocks <= kTraceScratchDoubles, "scratch holds every partial sum");
+    const int same = (PA == PB) ? 1 : 0;
+    hipStream_t st = ctx->stream;
+#define LAUNCH_B(BC)                                                                                       \
+    k_trace_products<1, BC><<<grid, kThreads, 0, st>>>(1, PA->b, PA->nnzb, PA->cols.as<int>(),           \
+                                                       PA->rowidx.as<int>(), PA->tmap.as<int>(), same,   \
+                                                       PB->rowptr.as<int>(), PB->cols.as<int>(), pa, pb, \
+                                                       ptr)
+    if (PA->b == 9) LAUNCH_B(9);
+    else if (PA->b == 4) LAUNCH_B(4);
+    else LAUNCH_B(0);
+#undef LAUNCH_B
+    BSM_HIP_TRY(hipGetLastError());
+    k_finish_to<<<1, kThreads, 0, st>>>(grid, ptr, out_dev);
+    BSM_HIP_TRY(hipGetLastError());
 }
 
 void trace_set(Context *ctx, int kind, const bsm_pattern_s *P, const double *const *A, const double *const *B,
