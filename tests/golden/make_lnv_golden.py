@@ -18,7 +18,11 @@ iteration E, N, mu, alpha, beta, dE and Omega; 64 seeded sample blocks of the
 final S^-1 and L with their (row, column); the Frobenius norm of every block
 row of both; wall times and the thread count of this run.
 
-Usage:  python tests/golden/make_lnv_golden.py si512_b9_disp [si4096_b9 ...]
+Usage:  python tests/golden/make_lnv_golden.py [--checkpoint DIR] si512_b9_disp [si4096_b9 ...]
+
+With --checkpoint DIR the state after Hotelling and after every LNV iteration
+is saved there (raw arrays), and a rerun resumes from it: the resumed run
+computes the same bits as an uninterrupted one.
 """
 import json
 import math
@@ -79,7 +83,21 @@ def log(*a):
     print(*a, flush=True)
 
 
-def run(name):
+def _save(ck, name, arr):
+    np.save(os.path.join(ck, name + ".tmp.npy"), arr)
+    os.replace(os.path.join(ck, name + ".tmp.npy"), os.path.join(ck, name + ".npy"))
+
+
+def _load(ck, name):
+    path = os.path.join(ck, name + ".npy")
+    return np.load(path) if os.path.exists(path) else None
+
+
+def run(name, ckdir=None):
+    ck = None
+    if ckdir:
+        ck = os.path.join(ckdir, name)
+        os.makedirs(ck, exist_ok=True)
     s = case_system(name)
     cut = s.cutoffs
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
@@ -92,20 +110,54 @@ def run(name):
     H = O.from_blocks(PS, s.b, s.H.rows, s.H.cols, s.H.blocks)
 
     t0 = time.perf_counter()
-    hr = O.hotelling_inverse(S, PZ, max_iter=HOT_MAX_ITER, tol=HOT_TOL)
-    hot_s = time.perf_counter() - t0
+    meta = json.load(open(os.path.join(ck, "meta.json"))) if ck and os.path.exists(os.path.join(ck, "meta.json")) \
+        else None
+    if meta is not None:
+        hr = O.HotellingResult(O.Matrix(PZ, s.b, _load(ck, "Z")), meta["hot_status"], meta["hot_iterations"],
+                               meta["hot_residuals"], meta["hot_alpha"])
+        hot_s = meta["hot_s"]
+        log(f"[{name}] Hotelling and {len(meta['iters'])} LNV iterations restored from {ck}")
+    else:
+        hr = O.hotelling_inverse(S, PZ, max_iter=HOT_MAX_ITER, tol=HOT_TOL)
+        hot_s = time.perf_counter() - t0
     log(f"[{name}] Hotelling: status {hr.status}, {hr.iterations} updates, residuals "
         f"{hr.residuals[0]:.6e} -> {hr.residuals[-1]:.6e}, {hot_s:.1f} s")
     if hr.status != O.OK:
         raise RuntimeError(f"Hotelling failed with status {hr.status}")
 
     t0 = time.perf_counter()
-    st = O.lnv_init(S, H, hr.Z, PL, s.n_electrons, tol_E=TOL_E)
-    init_s = time.perf_counter() - t0
+    if meta is not None and meta["iters"]:
+        st = O.lnv_init(S, H, hr.Z, PL, s.n_electrons, tol_E=TOL_E, L0=O.Matrix(PL, s.b, _load(ck, "L")))
+        st.n, st.E_prev, st.mu = meta["n"], meta["E_prev"], meta["mu"]
+        st.D_prev, st.g_prev, st.Mg_prev = (O.Matrix(PL, s.b, _load(ck, k)) for k in ("D", "g", "Mg"))
+        init_s = meta["init_s"]
+    else:
+        st = O.lnv_init(S, H, hr.Z, PL, s.n_electrons, tol_E=TOL_E)
+        init_s = time.perf_counter() - t0
     log(f"[{name}] initial L: {init_s:.1f} s")
-    iters, step_s = [], []
-    converged = False
-    for it in range(1, MAX_LNV + 1):
+    iters, step_s = (list(meta["iters"]), list(meta["step_s"])) if meta is not None else ([], [])
+
+    def checkpoint():
+        if not ck:
+            return
+        if st.D_prev is not None:
+            for k, M in (("L", st.L), ("D", st.D_prev), ("g", st.g_prev), ("Mg", st.Mg_prev)):
+                _save(ck, k, M.blocks)
+        else:
+            _save(ck, "Z", hr.Z.blocks)
+        m = {"hot_status": hr.status, "hot_iterations": hr.iterations, "hot_residuals": hr.residuals,
+             "hot_alpha": hr.alpha, "hot_s": hot_s, "init_s": init_s, "n": st.n, "E_prev": st.E_prev,
+             "mu": st.mu, "iters": iters, "step_s": step_s}
+        with open(os.path.join(ck, "meta.tmp.json"), "w") as f:
+            json.dump(m, f)
+        os.replace(os.path.join(ck, "meta.tmp.json"), os.path.join(ck, "meta.json"))
+
+    if meta is None:
+        checkpoint()
+    converged = bool(iters) and abs(iters[-1]["dE"]) < TOL_E and len(iters) > 1
+    for it in range(len(iters) + 1, MAX_LNV + 1):
+        if converged:
+            break
         t0 = time.perf_counter()
         r = O.lnv_step(st)
         step_s.append(time.perf_counter() - t0)
@@ -115,6 +167,7 @@ def run(name):
                       "dE": r.dE, "Omega": r.Omega})
         log(f"[{name}] LNV {it:3d}  E={r.E:.12f}  dE={r.dE:+.3e}  N={r.N:.10f}  mu={r.mu:+.6e}  "
             f"alpha={r.alpha:.6e}  {step_s[-1]:.1f} s")
+        checkpoint()
         if r.converged:
             converged = True
             break
@@ -146,5 +199,9 @@ def run(name):
 
 
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["si512_b9_disp"]:
-        run(name)
+    args = sys.argv[1:]
+    ckdir = None
+    if args[:1] == ["--checkpoint"]:
+        ckdir, args = args[1], args[2:]
+    for name in args or ["si512_b9_disp"]:
+        run(name, ckdir)
