@@ -578,10 +578,41 @@ def cpu_baseline(args):
     t0 = time.perf_counter()
     O.multiply_truncate(1.0, X, X, 0.0, C, 0, nrows)     # OpenMP over the rows
     dt = time.perf_counter() - t0
-    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"output block-rows 0..{nrows - 1} of {P.natoms} of the {rx:g} A x {rx:g} A -> {rx:g} A "
-                      f"product (the class holding ~90% of LNV flops), random FP64 blocks, "
-                      f"{flops / 1e9:.1f} GFLOP in {dt:.1f} s"}
+    out = {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"output block-rows 0..{nrows - 1} of {P.natoms} of the {rx:g} A x {rx:g} A -> {rx:g} A "
+                     f"product (the class holding ~90% of LNV flops), random FP64 blocks, "
+                     f"{flops / 1e9:.1f} GFLOP in {dt:.1f} s",
+           "cpu": host_cpu(),
+           "w_class_product_s_est": round(dt * float(tri.sum()) / float(tri[:nrows].sum()), 2)}
+    g = stored_oracle_solve(args.workload)
+    if g is not None:
+        t = g["timing"]
+        out["converged_solve"] = {
+            "s": round(t["solve_s"], 1), "lnv_iteration_s_mean": round(t["lnv_s"] / len(t["lnv_step_s"]), 1),
+            "hotelling_s": round(t["hotelling_s"], 1), "threads": t["threads"], "cpu": t["cpu"],
+            "note": "the full oracle solve of the same system, measured once on the build host "
+                    "(tests/golden/make_lnv_golden.py), not on this machine"}
+    return out
+
+
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def stored_oracle_solve(workload: str):
+    """The stored FP64 oracle solve of the benchmarked system (tests/golden), if present."""
+    path = os.path.join(ROOT, "tests", "golden", f"lnv_{workload}.json")
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
 
 
 KERNEL_SOURCES = ("paper_2205_08941_amd/csrc/product.hip", "paper_2205_08941_amd/csrc/tiles.h")
@@ -696,6 +727,8 @@ def main():
             if res.converged:
                 break
         torch.cuda.synchronize()
+        if res is None or not res.converged:
+            raise RuntimeError(f"[{tag}] LNV did not converge to |dE| < {args.tol_e:g} Ha in {it} iterations")
         return dict(seconds=time.perf_counter() - t, flops=flops, lnv_iterations=it,
                     hotelling_iterations=hr.iterations, E=res.E, N=res.N, converged=res.converged)
 
@@ -768,6 +801,15 @@ def main():
              "tflops": round(st["flops"] / (st["ms"] * 1e-3) / 1e12, 3), "ms": round(st["ms"], 2)}
             for st in stats],
     }
+    g = stored_oracle_solve(args.workload)
+    if g is not None:
+        Eo = g["lnv"]["E_final"]
+        out["oracle"] = {"E_Ha": Eo, "abs_dE_Ha": abs(runs[-1]["E"] - Eo),
+                         "rel_dE": abs(runs[-1]["E"] - Eo) / abs(Eo),
+                         "lnv_iterations": len(g["lnv"]["iterations"]),
+                         "hotelling_iterations": g["hotelling"]["iterations"],
+                         "source": f"tests/golden/lnv_{args.workload}.json (FP64 CPU oracle, same seeded system)"}
+        log(f"[oracle] E = {Eo:.10f} Ha, |dE| = {out['oracle']['abs_dE_Ha']:.3e} Ha")
     if not args.no_cpu_baseline:
         log("[cpu] timing the oracle on a sample of the dominant product")
         out["cpu_baseline"] = cpu_baseline(args)

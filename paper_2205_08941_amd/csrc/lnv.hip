@@ -278,10 +278,18 @@ extern "C" int lnv_state_reset_guess(lnv_state *st, const lnv_params *prm, const
         *out = lnv_guess_result{};
         lnv_params p = *prm;
         p.init_from_z = 1;
-        st->reset(p);                       // L = c mask_L(Z); products in FP64
+        st->reset(p);                       // L = c mask_L(Z) (formed with FP64 products)
         st->flops = 0.0;
         Context *c = st->c;
         const int64_t nl = nelems(st->PL);
+        // both energies of the accept test with FP64 products, whatever the state's
+        // product precision; that precision is restored on every exit
+        struct PrecGuard {
+            lnv_state_s *s;
+            int p;
+            ~PrecGuard() { s->prec = p; }
+        } guard{st, prm->product_precision};
+        st->prec = BSM_F64;
         st->energy(out->E_plain, out->N_plain);
         BSM_HIP_TRY(hipMemcpyAsync(st->t1.d(), st->L, sizeof(double) * nl, hipMemcpyDeviceToDevice, c->stream));
         axpby(c, nl, 1.0, (const double *)dL->blocks, 1.0, st->L);
@@ -294,7 +302,6 @@ extern "C" int lnv_state_reset_guess(lnv_state *st, const lnv_params *prm, const
         BSM_HIP_TRY(hipStreamSynchronize(c->stream));
         out->product_flops = st->init_flops + st->flops;
         st->flops = 0.0;
-        st->prec = prm->product_precision;
         return BSM_OK;
     } catch (const Error &e) {
         return fail(e.code, e.msg);
