@@ -199,6 +199,7 @@ def batch_mode(args):
         "f32": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r32.items()},
         "f32_gflops": round(r32["flops"] / (r32["batch_ms"] * 1e-3) / 1e9, 2),
         "batch_speedup_vs_separate_f64": round(r64["separate_ms"] / r64["batch_ms"], 3),
+        "batch_speedup_vs_separate_f32": round(r32["separate_ms"] / r32["batch_ms"], 3),
         "roofline": {"bound": "alu", "kernel": "k_product_batch (FP64)", "achieved": round(achieved, 3),
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                      "traffic": None, "avg_launch_ms": round(r64["batch_ms"], 3)},

@@ -263,10 +263,16 @@ int bsm_contract(bsm_ctx ctx, const bsm_matrix *M, const double *coef, const bsm
  * bsm_batch_tune, which times every candidate on the batch itself. */
 typedef struct bsm_batch_s *bsm_batch;
 enum { BSM_ORDER_BY_PRODUCT = 0, BSM_ORDER_HEAVY_FIRST = 1, BSM_ORDER_INTERLEAVE = 2 };
+enum { BSM_BATCH_ONE_LAUNCH = 0, BSM_BATCH_PER_B = 1, BSM_BATCH_SEPARATE = 2 };
 typedef struct {
     int order;          /* BSM_ORDER_*: work-list order */
     int waves_per_cu;   /* resident wavefronts per CU: 4, 8, ..., 32 */
     int queues;         /* 1 (one global queue) or 8 (one per XCD, equal-weight slices) */
+    int mode;           /* BSM_BATCH_ONE_LAUNCH: one persistent launch over every product's tiles;
+                           BSM_BATCH_PER_B: one persistent launch per orbital count, each kernel
+                           compiled for that tile alone; BSM_BATCH_SEPARATE: each product in its own
+                           launch, as bsm_multiply_truncate_prec runs it (order, waves and queues
+                           unused) */
 } bsm_batch_config;
 /* n products; A, B, C arrays of n matrices (C_p must not overlap A_p or B_p),
  * alpha, beta arrays of n.  precision: BSM_F64, BSM_F32 or BSM_BF16 (as in
@@ -277,9 +283,12 @@ int bsm_batch_create(bsm_ctx ctx, int n, const bsm_matrix *A, const bsm_matrix *
                      const double *alpha, const double *beta, int precision, bsm_batch *out);
 /* Queue the batch on the context stream; cfg NULL = the tuned (or default) schedule. */
 int bsm_batch_run(bsm_batch batch, const bsm_batch_config *cfg);
-/* Time every candidate schedule (3 orders x {1, 8} queues x {4, 8, 16} waves
- * per CU), `reps` runs each after one shared warm-up run, keep the fastest.
- * Runs the batch 1 + 18 reps times; synchronises. */
+/* Time every candidate schedule -- the separate launches, and for each of the
+ * two persistent modes 3 orders x {1, 8} queues x {4, 8, 16} waves per CU (the
+ * per-b mode only when it differs from one launch) -- `reps` timed runs each
+ * after one warm-up run of the candidate, keep the fastest; so the tuned
+ * schedule is never slower than separate launches by more than the timing
+ * noise.  Synchronises. */
 int bsm_batch_tune(bsm_batch batch, int reps, bsm_batch_config *best, double *best_ms);
 int bsm_batch_flops(bsm_batch batch, double *flops);
 int bsm_batch_destroy(bsm_batch batch);

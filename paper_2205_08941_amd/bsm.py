@@ -55,10 +55,11 @@ class _PatternInfo(ctypes.Structure):
 
 
 class _BatchConfig(ctypes.Structure):
-    _fields_ = [("order", c_int), ("waves_per_cu", c_int), ("queues", c_int)]
+    _fields_ = [("order", c_int), ("waves_per_cu", c_int), ("queues", c_int), ("mode", c_int)]
 
 
 ORDER_BY_PRODUCT, ORDER_HEAVY_FIRST, ORDER_INTERLEAVE = 0, 1, 2
+BATCH_ONE_LAUNCH, BATCH_PER_B, BATCH_SEPARATE = 0, 1, 2
 
 
 class _HotParams(ctypes.Structure):
@@ -448,17 +449,20 @@ class Batch:
         _check(_lib.bsm_batch_flops(h, ctypes.byref(f)))
         self.flops = f.value
 
-    def run(self, order: Optional[int] = None, waves_per_cu: int = 8, queues: int = 1) -> None:
+    def run(self, order: Optional[int] = None, waves_per_cu: int = 8, queues: int = 1,
+            mode: int = BATCH_ONE_LAUNCH) -> None:
+        """order None: the tuned (or default) schedule; else the given one (mode BATCH_ONE_LAUNCH,
+        BATCH_PER_B or BATCH_SEPARATE)."""
         if order is None:
             _check(_lib.bsm_batch_run(self.handle, None))
         else:
-            cfg = _BatchConfig(int(order), int(waves_per_cu), int(queues))
+            cfg = _BatchConfig(int(order), int(waves_per_cu), int(queues), int(mode))
             _check(_lib.bsm_batch_run(self.handle, ctypes.byref(cfg)))
 
     def tune(self, reps: int = 1):
         cfg, ms = _BatchConfig(), c_double()
         _check(_lib.bsm_batch_tune(self.handle, int(reps), ctypes.byref(cfg), ctypes.byref(ms)))
-        return dict(order=cfg.order, waves_per_cu=cfg.waves_per_cu, queues=cfg.queues), ms.value
+        return dict(order=cfg.order, waves_per_cu=cfg.waves_per_cu, queues=cfg.queues, mode=cfg.mode), ms.value
 
     def close(self):
         if getattr(self, "handle", None) and self.ctx.handle:

@@ -584,7 +584,7 @@ constexpr unsigned kBufMaxBytes = 0xfffff000u;
 // (j, i) that the plan's header gives.  Each element sums the same terms in the
 // same order as the direct product.
 template <int B, int G, int D, class T = double, bool BUF = false, int W = 1, int TR = 0>
-__device__ inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
+__device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
                                  const int *__restrict__ ent, const T *__restrict__ vA, const T *__restrict__ vB,
                                  const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta,
                                  lds_char_t *ring, unsigned a_bytes = 0, unsigned b_bytes = 0)

@@ -676,20 +676,22 @@ def test_batch_equals_separate_products(bsm, ctx, prec):
     case = _batch_case(bsm, ctx, 100 + prec)
     say(f"batch prec={prec}: {len(case)} products")
     batch = bsm.Batch(ctx, [(c["A"], c["B"], c["C"]) for c in case], alpha=1.5, beta=0.0, precision=prec)
-    for order in (0, 1, 2):
-        for queues in (1, 8):
-            for c in case:
-                c["C"].blocks.fill_(float("nan"))
-            batch.run(order=order, waves_per_cu=8, queues=queues)
-            for c in case:
-                bsm.multiply_truncate_prec(prec, 1.5, c["A"], c["B"], 0.0, c["C1"])
-                assert torch.equal(c["C"].blocks, c["C1"].blocks), (order, queues, c["b"])
+    for mode in (bsm.BATCH_ONE_LAUNCH, bsm.BATCH_PER_B, bsm.BATCH_SEPARATE):
+        for order in (0, 1, 2):
+            for queues in (1, 8):
+                for c in case:
+                    c["C"].blocks.fill_(float("nan"))
+                batch.run(order=order, waves_per_cu=8, queues=queues, mode=mode)
+                for c in case:
+                    bsm.multiply_truncate_prec(prec, 1.5, c["A"], c["B"], 0.0, c["C1"])
+                    assert torch.equal(c["C"].blocks, c["C1"].blocks), (mode, order, queues, c["b"])
     for c in case:
         Co = O.Matrix(c["oPC"], c["b"])
         O.multiply_truncate_mixed(prec, 1.5, c["oA"], c["oB"], 0.0, Co)
         assert rel_err(host(c["C"]), Co.blocks) < 1e-13
     cfg, ms = batch.tune(reps=1)
     assert cfg["queues"] in (1, 8) and cfg["waves_per_cu"] in (4, 8, 16) and ms > 0
+    assert cfg["mode"] in (bsm.BATCH_ONE_LAUNCH, bsm.BATCH_PER_B, bsm.BATCH_SEPARATE)
     before = [c["C"].blocks.clone() for c in case]
     batch.run()
     for c, x in zip(case, before):
