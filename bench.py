@@ -45,13 +45,19 @@ def parse():
                     help="batch64: 64 uneven systems (512-4096 atoms, b = 4 and 9), the 16 A x 16 A -> 16 A "
                          "product of each, per-product launches against one tuned persistent launch; "
                          "si4096_b9_mixed: the solve with BF16 then FP32 products and 3 FP64 steps against "
-                         "the FP64 solve; guess: networks trained on 512-atom displaced frames, a 4096-atom "
+                         "the FP64 solve; guess: networks trained on 4096-atom displaced frames, held-out 4096- and 32768-atom "
                          "displaced frame solved from the learned and from the plain starts; invsqrt: "
                          "truncated S^-1/2 and S^1/2 of the 4096-atom overlap (coupled Newton-Schulz); forces: "
                          "forces of a converged 4096-atom displaced frame; contract: the 4096-atom system "
                          "contracted to 4 on-site support functions per atom and solved, against the 9-orbital solve")
-    ap.add_argument("--guess-train", type=int, default=12, help="training frames of the guess workload")
-    ap.add_argument("--guess-cells", type=int, default=8, help="cells per side of the guess test frame")
+    ap.add_argument("--guess-train", type=int, default=64, help="training frames of the guess workload")
+    ap.add_argument("--guess-train-cells", type=int, default=8,
+                    help="cells per side of the guess training frames (8: 4096 atoms)")
+    ap.add_argument("--guess-sample-frac", type=float, default=0.25,
+                    help="fraction of each training frame's pair samples kept")
+    ap.add_argument("--guess-cells", type=int, default=16,
+                    help="cells per side of the large guess test frame (16: 32768 atoms); a frame of the "
+                         "training size is also compared")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--max-lnv", type=int, default=300)
     ap.add_argument("--tol-e", type=float, default=1e-8)
@@ -522,39 +528,83 @@ def invsqrt_cpu_baseline(s, updates):
 
 
 def guess_mode(args):
-    """Learned starts: train on 512-atom displaced frames, solve a larger held-out frame both ways."""
-    import torch
+    """Learned starts: networks trained on plain solves of displaced frames (one solver state
+    alive at a time), then held-out frames solved from the learned and from the plain starts."""
+    import functools
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
     import synth
+    nt = args.guess_train_cells
+    # the frames' S and H are generated on the host by worker processes, started before this
+    # process loads the GPU library or touches the GPU (the workers never do) and kept ahead of
+    # the solves
+    pool = ProcessPoolExecutor(max_workers=8, mp_context=multiprocessing.get_context("spawn"))
+    gen = functools.partial(synth.displaced_frame, (nt, nt, nt), 9)
+    futures = [pool.submit(gen, seed=10000 + k) for k in range(args.guess_train)]
+    big = pool.submit(functools.partial(synth.displaced_frame, (args.guess_cells,) * 3, 9), seed=20000)
+    import torch
     import paper_2205_08941_amd as bsm
     from paper_2205_08941_amd import guess
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
     ctx = bsm.Context(0)
     t = time.perf_counter()
-    frames = [guess.Frame(ctx, synth.displaced_frame((4, 4, 4), 9, seed=10000 + k)) for k in range(args.guess_train)]
-    netZ, netL, info = guess.train_guess(ctx, frames, epochs=30, batch=4096, lr=1e-3, log=log)
+
+    def frame(k):
+        return lambda: guess.Frame(ctx, futures[k].result())
+
+    netZ, netL, info = guess.train_guess(ctx, [frame(k) for k in range(args.guess_train)], epochs=30, batch=4096,
+                                         lr=1e-3, log=log, sample_frac=args.guess_sample_frac, close_frames=True)
     train_s = time.perf_counter() - t
     gen_s = sum(r["seconds"] for r in info["solves"])
-    for f in frames:
-        f.close()
-    del frames
     torch.cuda.empty_cache()
-    n = args.guess_cells
-    f = guess.Frame(ctx, synth.displaced_frame((n, n, n), 9, seed=20000))
-    log(f"[guess] trained in {train_s:.1f} s ({gen_s:.1f} s of solves); test frame {f.sys.natoms} atoms")
-    f.solve_plain(tol_E=args.tol_e)            # warm-up: patterns, plans
-    p = f.solve_plain(tol_E=args.tol_e)
-    g = f.solve_guess(netZ, netL, tol_E=args.tol_e, precision=bsm.BF16)
-    log(f"[guess] plain {p['hotelling']} + {p['lnv']} in {p['seconds']:.2f} s; learned {g['hotelling']} + "
-        f"{g['lnv']} in {g['seconds']:.2f} s; dE {g['E'] - p['E']:.2e} Ha")
-    res = {"metric": f"s per converged LNV solve, {f.sys.natoms}-atom 9-orb displaced frame, learned start",
-           "value": round(g["seconds"], 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
-           "ms_per_step": round(g["seconds"] * 1e3, 1), "higher_is_better": False, "scaling": "weak",
+    log(f"[guess] trained in {train_s:.1f} s ({gen_s:.1f} s of solves)")
+
+    def compare(n, seed):
+        sy = big.result() if n == args.guess_cells else synth.displaced_frame((n, n, n), 9, seed=seed)
+        f = guess.Frame(ctx, sy)
+        # a 32768-atom LNV state (~220 GB) and Hotelling's temporaries do not fit together:
+        # every solve of such a frame starts by releasing the previous one's state (both the
+        # plain and the learned start pay the allocation)
+        fresh = f.sys.natoms > 4096
+        log(f"[guess] test frame {f.sys.natoms} atoms: plain solve (plans)")
+        f.solve_plain(tol_E=args.tol_e, fresh_state=fresh)            # warm-up: patterns, plans
+        log(f"[guess] test frame {f.sys.natoms} atoms: plain solve (timed)")
+        p = f.solve_plain(tol_E=args.tol_e, fresh_state=fresh)
+        log(f"[guess] test frame {f.sys.natoms} atoms: learned start (timed)")
+        g = f.solve_guess(netZ, netL, tol_E=args.tol_e, precision=bsm.BF16, fresh_state=fresh)
+        log(f"[guess] {f.sys.natoms} atoms: plain {p['hotelling']} + {p['lnv']} in {p['seconds']:.2f} s; learned "
+            f"{g['hotelling']} + {g['lnv']} in {g['seconds']:.2f} s; dE {g['E'] - p['E']:.2e} Ha")
+        natoms = f.sys.natoms
+        f.close()
+        del f
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return dict(natoms=natoms, plain=p, learned=g, dE_per_atom_Ha=abs(g["E"] - p["E"]) / natoms,
+                    speedup_vs_plain=round(p["seconds"] / g["seconds"], 3), state_released_per_solve=fresh)
+
+    results = {}
+    for n in sorted({nt, args.guess_cells}):
+        try:
+            results[8 * n ** 3] = compare(n, 20000)
+        except Exception as e:   # e.g. device memory: reported, not hidden
+            log(f"[guess] {8 * n ** 3}-atom comparison failed: {e}")
+            results[8 * n ** 3] = {"unmeasured": str(e)[:300]}
+    pool.shutdown()
+    large = results[8 * args.guess_cells ** 3]
+    head = large if "learned" in large else results[8 * nt ** 3]
+    res = {"metric": f"s per converged LNV solve, {head['natoms']}-atom 9-orb displaced frame, learned start",
+           "value": round(head["learned"]["seconds"], 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": round(head["learned"]["seconds"] * 1e3, 1), "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64 solve, bf16 network", "data": "synthetic",
-           "config": {"workload": f"train on {args.guess_train} 512-atom frames (sigma 0.05 A), test on "
-                                  f"{f.sys.natoms} atoms", "train_samples_L": info["samples_L"],
+           "config": {"workload": f"train on {args.guess_train} {8 * nt ** 3}-atom frames (sigma 0.05 A, "
+                                  f"{args.guess_sample_frac:g} of each frame's pair samples), test on "
+                                  f"{sorted(results)} atoms", "train_samples_L": info["samples_L"],
                       "train_samples_Z": info["samples_Z"]},
-           "plain": p, "learned": g, "dE_per_atom_Ha": abs(g["E"] - p["E"]) / f.sys.natoms,
-           "speedup_vs_plain": round(p["seconds"] / g["seconds"], 3), "train_seconds": round(train_s, 2),
-           "train_solve_seconds": round(gen_s, 2),
+           "tests": {str(k): v for k, v in results.items()},
+           "train_seconds": round(train_s, 2), "train_solve_seconds": round(gen_s, 2),
+           "train_iterations": [[r["hotelling"], r["lnv"]] for r in info["solves"]],
            "loss_L": [info["losses_L"][0], info["losses_L"][-1]], "loss_Z": [info["losses_Z"][0], info["losses_Z"][-1]]}
     print(json.dumps(res), flush=True)
 
@@ -658,6 +708,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU domain "
               "decomposition is designed but not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "guess" and args.mode == "solve":
+        guess_mode(args)   # starts host worker processes before the GPU library is loaded
+        return
     import numpy as np
     import torch
     import synth
@@ -674,9 +727,6 @@ def main():
         return
     if args.workload == "si4096_b9_mixed":
         mixed_mode(args)
-        return
-    if args.workload == "guess":
-        guess_mode(args)
         return
     if args.workload == "invsqrt":
         invsqrt_mode(args)

@@ -146,14 +146,24 @@ struct lnv_state_s {
             return;
         }
         const bsm_pattern_s *PT = derived_pattern_cached(PZ, PZ->cutoff + PS->cutoff);
-        Mat T(c, PT), T2(c, PT);
+        // T and T2 live in the X and Y buffers when they fit (they are free until the first
+        // energy evaluation): no extra device memory next to the state, which at 32768 atoms
+        // would not fit beside it
+        Mat Tm, T2m;
+        double *tb = X.d(), *t2b = Y.d();
+        if (nelems(PT) > X.n()) {
+            Tm = Mat(c, PT);
+            T2m = Mat(c, PT);
+            tb = Tm.d();
+            t2b = T2m.d();
+        }
         flops = 0.0;
-        mul(1.0, PZ, Z, PS, S, 0.0, T.p, T.d());
-        mul(1.0, T.p, T.d(), T.p, T.d(), 0.0, T2.p, T2.d());
+        mul(1.0, PZ, Z, PS, S, 0.0, PT, tb);
+        mul(1.0, PT, tb, PT, tb, 0.0, PT, t2b);
         init_flops = flops;
-        const double *a[2] = {T.d(), T2.d()}, *b[2] = {T.d(), T.d()};
+        const double *a[2] = {tb, t2b}, *b[2] = {tb, tb};
         double tt[2];
-        trace_products(c, 2, T.p, a, T.p, b, tt);
+        trace_products(c, 2, PT, a, PT, b, tt);
         BSM_REQUIRE(std::isfinite(tt[0]) && std::isfinite(tt[1]), BSM_ENONFINITE, "initial traces are not finite");
         const double nb = (double)PL->natoms * PL->b;
         const double scale = initial_scale(nb, p.n_electrons, tt[0], tt[1]);

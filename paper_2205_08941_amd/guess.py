@@ -63,8 +63,17 @@ class Frame:
                 return it, res
         raise RuntimeError(f"LNV did not converge in {max_iter} steps")
 
-    def solve_plain(self, tol_E: float = 1e-8, max_iter: int = 300) -> dict:
-        """Hotelling from I / rho, LNV from c mask_L(Z); keeps the plain starts for targets."""
+    def release_state(self):
+        """Free the LNV solver state (its matrices return to the allocator): for systems whose
+        state and Hotelling's temporaries do not fit on the device together."""
+        self.close()
+        torch.cuda.empty_cache()
+
+    def solve_plain(self, tol_E: float = 1e-8, max_iter: int = 300, fresh_state: bool = False) -> dict:
+        """Hotelling from I / rho, LNV from c mask_L(Z); keeps the plain starts for targets.
+        fresh_state: release the previous solve's LNV state before Hotelling runs."""
+        if fresh_state:
+            self.release_state()
         t = time.perf_counter()
         hr = B.hotelling_inverse(self.S, self.Z, init_given=B.INIT_PLAIN)
         lnv = self._lnv(tol_E)
@@ -76,8 +85,11 @@ class Frame:
         return dict(hotelling=hr.iterations, lnv=steps, E=res.E, N=res.N, seconds=time.perf_counter() - t)
 
     def solve_guess(self, netZ: "GuessNet", netL: "GuessNet", tol_E: float = 1e-8, max_iter: int = 300,
-                    precision: int = B.BF16, n_tol: float = 0.01) -> dict:
-        """Hotelling and LNV from the networks' corrected starts (each guarded by the plain one)."""
+                    precision: int = B.BF16, n_tol: float = 0.01, fresh_state: bool = False) -> dict:
+        """Hotelling and LNV from the networks' corrected starts (each guarded by the plain one).
+        fresh_state: as in solve_plain."""
+        if fresh_state:
+            self.release_state()
         t = time.perf_counter()
         XZ = B.pair_descriptors(self.PS, self.PZ)
         netZ.net.predict_blocks(XZ, self.Z, scale=netZ.scale, beta=0.0, precision=precision)
@@ -127,21 +139,49 @@ class GuessNet:
     scale: float
 
 
-def train_guess(ctx: B.Context, frames: List[Frame], epochs: int = 40, batch: int = 4096, lr: float = 1e-3,
-                seed: int = 0, log=None):
-    """Train the Z and L networks on plain solves of `frames` (solved here).  Returns
-    (netZ, netL, info) with per-epoch losses and the solves' iteration counts."""
-    solves = [f.solve_plain() for f in frames]
-    rz, rl = frames[0].correction_rms()
-    scale_Z, scale_L = max(rz, 1e-30), max(rl, 1e-30)
-    data = [f.samples(scale_Z, scale_L) for f in frames]
+def train_guess(ctx: B.Context, frames, epochs: int = 40, batch: int = 4096, lr: float = 1e-3,
+                seed: int = 0, log=None, sample_frac: float = 1.0, close_frames: bool = False):
+    """Train the Z and L networks on plain solves of `frames` (solved here, one after the
+    other).  `frames` holds Frames or zero-argument callables that build one; with
+    close_frames each frame is released once its samples are taken, so only one solver
+    state is alive at a time.  sample_frac < 1 keeps that seeded fraction of each frame's
+    pair samples.  Returns (netZ, netL, info) with per-epoch losses and the solves'
+    iteration counts."""
+    solves, data = [], []
+    scale_Z = scale_L = None
+    b2 = None
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(seed)
+
+    def keep(X, T):
+        if sample_frac >= 1.0:
+            return X, T
+        n = X.shape[0]
+        idx = torch.randperm(n, generator=gen)[:max(1, int(round(sample_frac * n)))].to(X.device)
+        return X.index_select(0, idx), T.index_select(0, idx)
+
+    for k, fr in enumerate(frames):
+        f = fr() if callable(fr) else fr
+        solves.append(f.solve_plain())
+        if scale_Z is None:
+            rz, rl = f.correction_rms()
+            scale_Z, scale_L = max(rz, 1e-30), max(rl, 1e-30)
+        XZ, TZ, XL, TL = f.samples(scale_Z, scale_L)
+        data.append(keep(XZ, TZ) + keep(XL, TL))
+        b2 = f.sys.b ** 2
+        if log:
+            r = solves[-1]
+            log(f"[guess] training frame {k}: {f.sys.natoms} atoms, {r['hotelling']} + {r['lnv']} steps in "
+                f"{r['seconds']:.2f} s, {data[-1][0].shape[0]} Z and {data[-1][2].shape[0]} L samples kept")
+        if close_frames:
+            f.close()
+            del f
+            torch.cuda.empty_cache()
     XZ = torch.cat([d[0] for d in data])
     TZ = torch.cat([d[1] for d in data])
     XL = torch.cat([d[2] for d in data])
     TL = torch.cat([d[3] for d in data])
-    b2 = frames[0].sys.b ** 2
-    gen = torch.Generator(device="cpu")
-    gen.manual_seed(seed)
+    del data
     out = []
     for name, X, T, scale in (("Z", XZ, TZ, scale_Z), ("L", XL, TL, scale_L)):
         net = B.MLP(ctx, b2, init_params(b2, seed + (name == "L")))

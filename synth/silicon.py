@@ -186,8 +186,12 @@ def _fold(i, j, blocks, natoms):
     key = i * natoms + j
     order = np.argsort(key, kind="stable")
     key, blocks = key[order], blocks[order]
-    uk, start = np.unique(key, return_index=True)
-    summed = np.add.reduceat(blocks, start, axis=0) if len(blocks) else blocks
+    uk, start, count = np.unique(key, return_index=True, return_counts=True)
+    # images of one pair added in list order, first + second + ... (most pairs have one)
+    summed = blocks[start]
+    for m in range(1, int(count.max()) if len(count) else 0):
+        sel = np.nonzero(count > m)[0]
+        summed[sel] += blocks[start[sel] + m]
     return (uk // natoms).astype(np.int32), (uk % natoms).astype(np.int32), summed
 
 
