@@ -83,8 +83,15 @@ int bsm_mlp_destroy(bsm_mlp net);
 /* Descriptors of every slot of P, in slot order: desc is device memory of
  * nnzb(P) x 32 floats.  Atom frames come from the four nearest neighbours in
  * `neighbours` (a pattern over the same positions whose every row holds at
- * least four atoms besides the diagonal, e.g. the overlap pattern).  Values
- * are computed in FP64 and rounded to FP32.  desc must be 16-byte aligned.
+ * least four atoms besides the diagonal, e.g. the overlap pattern).  Per slot
+ * (i, j) with minimum-image vector r, d = |r|, cutoff r_c of P: r / r_c, d / r_c,
+ * (d / r_c)^2, exp(-d / 1.5 A), the sublattice signs of i and j, the cosines of r
+ * with the four bond directions of i and of j, 10 (bond length - ideal) of
+ * those bonds for i and j, 10 x the neighbour centroids of i and j, and
+ * 10 (rho - rho_0) for i and j, rho the sum of exp(-d / 1.5 A) over the atom's
+ * row of `neighbours` (its environment) and rho_0 its value for an ideal-lattice
+ * atom over a 6 A pattern.  Values are computed in FP64 and rounded to FP32.
+ * desc must be 16-byte aligned.
  * Errors: BSM_EPATTERN (different atoms), BSM_EINVAL (a row with fewer than
  * four neighbours, misaligned desc). */
 int bsm_pair_descriptors(bsm_ctx ctx, bsm_pattern neighbours, bsm_pattern P, float *desc);

@@ -55,9 +55,22 @@ def min_image(pos: np.ndarray, box: np.ndarray, i, j) -> np.ndarray:
     return d - box * np.rint(d / box)
 
 
-def atom_frames(pos: np.ndarray, box: np.ndarray):
-    """Sublattice sign s (N,), bond directions e (N, 4, 3), bond lengths l (N, 4)
-    and neighbour centroid c (N, 3) of every atom.
+# Overlap-weighted neighbour count of an atom of the ideal diamond lattice within
+# RHO_CUTOFF: the textbook coordination shells inside 6 A (4 at a sqrt(3)/4, 12 at
+# a/sqrt(2), 12 at a sqrt(11)/4, 6 at a, 12 at a sqrt(19)/4; the next, 24 at
+# a sqrt(27)/4 = 7.05 A, lies outside), each weighted by exp(-d / DECAY).
+RHO_CUTOFF = 6.0
+RHO0 = sum(n * np.exp(-5.43 * np.sqrt(q) / 4.0 / DECAY) for q, n in ((3, 4), (8, 12), (11, 12), (16, 6), (19, 12)))
+
+
+def atom_frames(pos: np.ndarray, box: np.ndarray, rho_cutoff: float = RHO_CUTOFF):
+    """Sublattice sign s (N,), bond directions e (N, 4, 3), bond lengths l (N, 4),
+    neighbour centroid c (N, 3) and environment density rho (N,) of every atom.
+
+    rho_i = sum over the atoms j != i with minimum-image d_ij^2 < rho_cutoff^2 of
+    exp(-d_ij / DECAY), added in ascending j: a collective measure of the
+    environment (how many neighbours, how close), which the pair terms alone
+    do not see.
 
     The four nearest neighbours are found by brute force over all atoms
     (minimum image), ordered by (squared distance, index).  With v_n their unit
@@ -71,10 +84,15 @@ def atom_frames(pos: np.ndarray, box: np.ndarray):
     e = np.zeros((n, 4, 3))
     l = np.zeros((n, 4))
     c = np.zeros((n, 3))
+    rho = np.zeros(n)
     for i in range(n):
         others = np.array([j for j in range(n) if j != i])
         v = min_image(pos, box, np.full(len(others), i), others)
         d2 = (v * v).sum(1)
+        acc = 0.0
+        for q in np.flatnonzero(d2 < rho_cutoff * rho_cutoff):   # ascending j
+            acc += float(np.exp(-np.sqrt(d2[q]) / DECAY))
+        rho[i] = acc
         order = np.lexsort((others, d2))[:4]
         u = v[order] / np.sqrt(d2[order])[:, None]
         dots = u @ TETRA.T                       # (4 neighbours, 4 directions)
@@ -85,13 +103,13 @@ def atom_frames(pos: np.ndarray, box: np.ndarray):
             e[i, a] = u[q]
             l[i, a] = np.sqrt(d2[order][q])
         c[i] = v[order].mean(axis=0)
-    return s, e, l, c
+    return s, e, l, c, rho
 
 
 def pair_descriptors(pos: np.ndarray, box: np.ndarray, rows: np.ndarray, cols: np.ndarray,
                      cutoff: float, frames) -> np.ndarray:
     """(nnz, 32) descriptors of the pattern slots (rows[k], cols[k]), in slot order."""
-    s, e, l, c = frames
+    s, e, l, c, rho = frames
     r = min_image(pos, box, rows, cols)
     d = np.sqrt((r * r).sum(1))
     rhat = np.where(d[:, None] > 0, r / np.where(d > 0, d, 1.0)[:, None], 0.0)
@@ -108,6 +126,8 @@ def pair_descriptors(pos: np.ndarray, box: np.ndarray, rows: np.ndarray, cols: n
     out[:, 20:24] = 10.0 * (l[cols] - BOND0)
     out[:, 24:27] = 10.0 * c[rows]
     out[:, 27:30] = 10.0 * c[cols]
+    out[:, 30] = 10.0 * (rho[rows] - RHO0)
+    out[:, 31] = 10.0 * (rho[cols] - RHO0)
     return out
 
 

@@ -85,9 +85,14 @@ __constant__ double kTetra[4][3] = {{1, 1, 1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1
 
 constexpr int kFrame = 24;   // doubles per atom frame
 constexpr double kBond0 = 2.3512589712747505;   // 5.43 sqrt(3) / 4 rounded to FP64: the ideal Si-Si bond, Angstrom
+// environment density of an ideal-lattice atom over a 6 A neighbour pattern: the five
+// diamond shells inside 6 A (4, 12, 12, 6, 12 atoms at 5.43 sqrt(q) / 4 A, q = 3, 8, 11,
+// 16, 19) weighted by exp(-d / 1.5 A)
+constexpr double kRho0 = 2.751647885181917;
 
 // Per atom (see the header): fr[24 i] = s, fr[24 i + 1 + 3 a + c] = e[a][c],
-// fr[24 i + 13 + a] = l[a], fr[24 i + 17 + c] = c_i[c].
+// fr[24 i + 13 + a] = l[a], fr[24 i + 17 + c] = c_i[c], fr[24 i + 20] = rho_i (the
+// sum over the row's other atoms of exp(-d / 1.5 A), in column order).
 __global__ void k_atom_frames(int n, const double *__restrict__ pos, double3 box, const int *__restrict__ rowptr,
                               const int *__restrict__ cols, double *__restrict__ fr, int *__restrict__ bad)
 {
@@ -97,6 +102,7 @@ __global__ void k_atom_frames(int n, const double *__restrict__ pos, double3 box
     int bj[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
     double bv[4][3] = {};
     int found = 0;
+    double rho = 0.0;
     for (int s = rowptr[i]; s < rowptr[i + 1]; ++s) {
         const int j = cols[s];
         if (j == i) continue;
@@ -104,6 +110,7 @@ __global__ void k_atom_frames(int n, const double *__restrict__ pos, double3 box
         double r[3];
         min_image(pos, box, i, j, r);
         const double d2 = norm2(r);
+        rho = dadd(rho, exp(-sqrt(d2) / 1.5));
         // insert (d2, j) into the sorted best-four list
         int at = 4;
         while (at > 0 && (d2 < bd[at - 1] || (d2 == bd[at - 1] && j < bj[at - 1]))) --at;
@@ -151,6 +158,7 @@ __global__ void k_atom_frames(int n, const double *__restrict__ pos, double3 box
         f[13 + a] = sqrt(bd[best]);
     }
     for (int c = 0; c < 3; ++c) f[17 + c] = dadd(dadd(dadd(bv[0][c], bv[1][c]), bv[2][c]), bv[3][c]) / 4.0;
+    f[20] = rho;
 }
 
 __global__ void k_pair_desc(int64_t nnz, const int *__restrict__ rowidx, const int *__restrict__ cols,
@@ -183,7 +191,8 @@ __global__ void k_pair_desc(int64_t nnz, const int *__restrict__ rowidx, const i
         v[24 + c] = (float)(10.0 * fi[17 + c]);
         v[27 + c] = (float)(10.0 * fj[17 + c]);
     }
-    v[30] = v[31] = 0.f;
+    v[30] = (float)(10.0 * (fi[20] - kRho0));
+    v[31] = (float)(10.0 * (fj[20] - kRho0));
     float4 *o = reinterpret_cast<float4 *>(X + (int64_t)kD * s);
     for (int q = 0; q < kD / 4; ++q) o[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
 }

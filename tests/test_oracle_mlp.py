@@ -87,7 +87,7 @@ def test_training_fits_a_linear_target():
 
 def test_frames_on_the_ideal_lattice():
     pos, box, sub = synth.diamond_positions((2, 2, 2))
-    s, e, l, c = M.atom_frames(pos, box)
+    s, e, l, c, _ = M.atom_frames(pos, box)
     assert np.array_equal(s, np.where(sub == 0, 1.0, -1.0))
     # every bond direction is exactly the sublattice's tetrahedral direction, every bond ideal
     assert np.allclose(e, s[:, None, None] * M.TETRA[None], atol=1e-12)
@@ -119,14 +119,35 @@ def test_descriptors_of_the_ideal_lattice():
     assert np.allclose(Xt[off, 3:6], X[off, 3:6], atol=1e-14)
     assert np.array_equal(Xt[off, 6], X[off, 7])
     assert np.allclose(Xt[off, 8:12], -X[off, 12:16], atol=1e-14)
-    # no strain on the ideal lattice, and the two padding features are zero
-    assert np.allclose(X[:, 16:32], 0.0, atol=1e-11)
+    # no strain on the ideal lattice
+    assert np.allclose(X[:, 16:30], 0.0, atol=1e-11)
+
+
+def test_environment_density_of_the_ideal_lattice():
+    # 3 x 3 x 3 cells (box 16.3 A): every atom sees the infinite lattice's shells inside 6 A, so
+    # its density is the textbook value and the environment features vanish; a 2 x 2 x 2 cell
+    # (box 10.86 A) folds the shell at a = 5.43 A onto 3 atoms and the one at a sqrt(19)/4 onto
+    # fewer atoms, so there the density is lower
+    pos, box, _ = synth.diamond_positions((3, 3, 3))
+    fr = M.atom_frames(pos, box)
+    assert np.allclose(fr[4], M.RHO0, rtol=1e-14)
+    assert M.RHO0 == pytest.approx(4 * np.exp(-2.3513 / 1.5) + 12 * np.exp(-3.8396 / 1.5) + 12 * np.exp(-4.5023 / 1.5)
+                                   + 6 * np.exp(-5.43 / 1.5) + 12 * np.exp(-5.9172 / 1.5), rel=1e-4)
+    n = len(pos)
+    X = M.pair_descriptors(pos, box, np.arange(n), np.arange(n), 8.0, fr)
+    assert np.allclose(X[:, 30:32], 0.0, atol=1e-12)
+    small = M.atom_frames(*synth.diamond_positions((2, 2, 2))[:2])
+    assert np.all(small[4] < M.RHO0 - 0.01)
+    # a displaced frame: an atom pushed toward its neighbours gains density
+    sy = synth.displaced_frame(3, 4, seed=10003, sigma=0.05)
+    fr2 = M.atom_frames(sy.positions, sy.box)
+    assert np.abs(fr2[4] - M.RHO0).max() > 1e-3 and np.abs(fr2[4] - M.RHO0).max() < 0.5
 
 
 def test_frames_of_a_displaced_frame_keep_the_sublattices():
     sy = synth.displaced_frame(2, 4, seed=10000, sigma=0.05)
     _, _, sub = synth.diamond_positions((2, 2, 2))
-    s, e, l, c = M.atom_frames(sy.positions, sy.box)
+    s, e, l, c, _ = M.atom_frames(sy.positions, sy.box)
     assert np.array_equal(s, np.where(sub == 0, 1.0, -1.0))
     # each hybrid slot holds a different neighbour, within a few degrees of the ideal direction
     cos = np.einsum("nac,ac->na", e, M.TETRA) * s[:, None]
