@@ -104,6 +104,33 @@ def test_pattern_rejects_bad_input(bsm, ctx):
     assert e.value.code == bsm.EINVAL
 
 
+def test_pattern_row_cap(bsm, ctx):
+    """Rows are sorted in LDS, so a row holds at most 8192 blocks: a cutoff past every
+    minimum-image distance gives rows of all atoms; 8192 atoms build (every row full,
+    columns in order), 8193 are refused before any row is written, and the context
+    stays usable."""
+    rng = np.random.default_rng(8192)
+    box = (40.0, 40.0, 40.0)
+    pos = rng.uniform(0.0, 40.0, (8193, 3))
+    say("pattern row cap: 8192 atoms, full rows")
+    P = gpat(bsm, ctx, pos[:8192], box, 100.0, 1)
+    rp, cols = P.to_host()
+    assert P.max_row == 8192
+    assert np.array_equal(rp, np.arange(8193, dtype=np.int64) * 8192)
+    full = np.arange(8192)
+    for i in (0, 4095, 8191):
+        assert np.array_equal(cols[rp[i]:rp[i + 1]], full)
+    del P
+    say("pattern row cap: 8193 atoms refused")
+    with pytest.raises(bsm.BSMError) as e:
+        gpat(bsm, ctx, pos, box, 100.0, 1)
+    assert e.value.code == bsm.EINVAL and "8192" in str(e.value)
+    P = gpat(bsm, ctx, pos[:64], box, 12.0, 4)
+    Po = O.create_pattern(pos[:64], box, 12.0)
+    rp, cols = P.to_host()
+    assert np.array_equal(rp, Po.rowptr) and np.array_equal(cols, Po.cols)
+
+
 # ------------------------------------------------------------------ products
 PRODUCT_CASES = [(6, 6, 8), (8, 6, 5), (3, 8, 6), (6, 8, 14), (12, 12, 12), (8, 8, 3)]
 
