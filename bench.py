@@ -267,6 +267,17 @@ def mixed_mode(args):
            "speedup_vs_f64": round(out["f64"]["seconds"] / out["mixed"]["seconds"], 3),
            "bf16_f64x5": out["bf16_f64x5"],
            "bf16_f64x5_speedup_vs_f64": round(out["f64"]["seconds"] / out["bf16_f64x5"]["seconds"], 3)}
+    g = stored_oracle_solve("si4096_b9")
+    if g is not None:
+        Eo = g["lnv"]["E_final"]
+        for tag in out:
+            out[tag]["dE_oracle_per_atom_Ha"] = abs(out[tag]["E"] - Eo) / s.natoms
+            out[tag]["within_1e-6_Ha_per_atom_of_oracle"] = out[tag]["dE_oracle_per_atom_Ha"] <= 1e-6
+        res["oracle"] = {"E_Ha": Eo, "idempotency_error": g["lnv"].get("idempotency_error"),
+                         "lnv_iterations": len(g["lnv"]["iterations"]),
+                         "source": "tests/golden/lnv_si4096_b9.json (FP64 CPU oracle, same seeded system)"}
+        for tag in out:
+            log(f"[oracle] {tag}: |E - E_oracle| / N = {out[tag]['dE_oracle_per_atom_Ha']:.3e} Ha")
     print(json.dumps(res), flush=True)
 
 

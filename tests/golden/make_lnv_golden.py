@@ -14,20 +14,27 @@ Cases:
 
 Stored per case (JSON): the Hotelling residual after every update, the
 Gershgorin scale and the update count; the initial-guess traces; per LNV
-iteration E, N, mu, alpha, beta, dE and Omega; 64 seeded sample blocks of the
+iteration E, N, mu, alpha, beta, dE and Omega; the idempotency error of the
+converged L; 64 seeded sample blocks of the
 final S^-1 and L with their (row, column); the Frobenius norm of every block
 row of both; wall times and the thread count of this run.
 
 Usage:  python tests/golden/make_lnv_golden.py [--checkpoint DIR] si512_b9_disp [si4096_b9 ...]
 
 With --checkpoint DIR the state after Hotelling and after every LNV iteration
-is saved there (raw arrays), and a rerun resumes from it: the resumed run
-computes the same bits as an uninterrupted one.
+is saved there (raw arrays), and so is every block product of the stage in
+progress (the state restore and each LNV iteration) as it completes: a rerun
+resumes from the last saved state and loads the saved products of the
+interrupted stage in call order instead of recomputing them.  The oracle is
+deterministic, so the resumed run computes the same bits as an uninterrupted
+one; the stored stage times add each loaded product's original compute time to
+the rerun's own.
 """
 import json
 import math
 import os
 import platform
+import shutil
 import sys
 import time
 
@@ -93,6 +100,56 @@ def _load(ck, name):
     return np.load(path) if os.path.exists(path) else None
 
 
+class ProductCache:
+    """Stands in for the oracle's `product` while a checkpointed stage runs: the
+    n-th product of the stage is saved on completion and, in a rerun of the same
+    stage, loaded instead of recomputed."""
+
+    def __init__(self, compute):
+        self.compute = compute
+        self.dir = None
+        self.n = 0
+        self.saved_s = 0.0      # original compute time of the products loaded
+        self.load_s = 0.0       # time spent loading them
+
+    def stage(self, path):
+        self.dir, self.n, self.saved_s, self.load_s = path, 0, 0.0, 0.0
+        if path:
+            os.makedirs(path, exist_ok=True)
+
+    def drop(self, path):
+        if path and os.path.isdir(path):
+            shutil.rmtree(path)
+
+    def __call__(self, A, B, pattern, prec=O.F64):
+        if not self.dir:
+            return self.compute(A, B, pattern, prec)
+        base = os.path.join(self.dir, f"p{self.n:03d}")
+        self.n += 1
+        if os.path.exists(base + ".json"):
+            t0 = time.perf_counter()
+            with open(base + ".json") as f:
+                m = json.load(f)
+            C = O.Matrix(pattern, A.b, np.load(base + ".npy"))
+            assert C.pattern.nnz == m["nnz"] and m["prec"] == prec
+            self.load_s += time.perf_counter() - t0
+            self.saved_s += m["s"]
+            return C
+        t0 = time.perf_counter()
+        C = self.compute(A, B, pattern, prec)
+        dt = time.perf_counter() - t0
+        np.save(base + ".tmp.npy", C.blocks)
+        os.replace(base + ".tmp.npy", base + ".npy")
+        with open(base + ".tmp.json", "w") as f:
+            json.dump({"s": dt, "nnz": int(pattern.nnz), "prec": prec}, f)
+        os.replace(base + ".tmp.json", base + ".json")
+        return C
+
+    def credit(self):
+        """Seconds the loaded products took when computed, less the time spent loading them."""
+        return self.saved_s - self.load_s
+
+
 def run(name, ckdir=None):
     ck = None
     if ckdir:
@@ -125,9 +182,14 @@ def run(name, ckdir=None):
     if hr.status != O.OK:
         raise RuntimeError(f"Hotelling failed with status {hr.status}")
 
+    cache = ProductCache(O.product)
+    if ck:
+        O.product = cache
     t0 = time.perf_counter()
     if meta is not None and meta["iters"]:
+        cache.stage(os.path.join(ck, f"restore{len(meta['iters'])}"))
         st = O.lnv_init(S, H, hr.Z, PL, s.n_electrons, tol_E=TOL_E, L0=O.Matrix(PL, s.b, _load(ck, "L")))
+        cache.stage(None)
         st.n, st.E_prev, st.mu = meta["n"], meta["E_prev"], meta["mu"]
         st.D_prev, st.g_prev, st.Mg_prev = (O.Matrix(PL, s.b, _load(ck, k)) for k in ("D", "g", "Mg"))
         init_s = meta["init_s"]
@@ -158,9 +220,12 @@ def run(name, ckdir=None):
     for it in range(len(iters) + 1, MAX_LNV + 1):
         if converged:
             break
+        step_dir = os.path.join(ck, f"step{it}") if ck else None
+        cache.stage(step_dir)
         t0 = time.perf_counter()
         r = O.lnv_step(st)
-        step_s.append(time.perf_counter() - t0)
+        step_s.append(time.perf_counter() - t0 + cache.credit())
+        cache.stage(None)
         if r.status != O.OK:
             raise RuntimeError(f"LNV step {it} failed with status {r.status}")
         iters.append({"E": r.E, "N": r.N, "mu": r.mu, "alpha": r.alpha, "beta": r.beta,
@@ -168,10 +233,17 @@ def run(name, ckdir=None):
         log(f"[{name}] LNV {it:3d}  E={r.E:.12f}  dE={r.dE:+.3e}  N={r.N:.10f}  mu={r.mu:+.6e}  "
             f"alpha={r.alpha:.6e}  {step_s[-1]:.1f} s")
         checkpoint()
+        if ck:
+            cache.drop(step_dir)
+            cache.drop(os.path.join(ck, f"restore{it - 1}"))
         if r.converged:
             converged = True
             break
     lnv_s = sum(step_s)
+    cache.stage(os.path.join(ck, "final") if ck else None)
+    e_idem = O.idempotency_error(st)
+    cache.stage(None)
+    log(f"[{name}] idempotency error of the converged L: {e_idem:.6e}")
     rng = np.random.default_rng(2205)
     out = {
         "case": name,
@@ -180,7 +252,7 @@ def run(name, ckdir=None):
         "hotelling": {"max_iter": HOT_MAX_ITER, "tol": HOT_TOL, "status": hr.status,
                       "iterations": hr.iterations, "alpha": hr.alpha, "residuals": hr.residuals},
         "lnv": {"tol_E": TOL_E, "max_iter": MAX_LNV, "converged": converged, "iterations": iters,
-                "E_final": iters[-1]["E"]},
+                "E_final": iters[-1]["E"], "idempotency_error": e_idem},
         "Z_samples": sample_blocks(st.Z, rng),
         "L_samples": sample_blocks(st.L, rng),
         "Z_row_norms": row_norms(st.Z),

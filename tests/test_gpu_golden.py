@@ -16,7 +16,8 @@ within 1e-10 relative), sampled S^-1 blocks and every S^-1 block-row norm within
 1e-10 of the result scale; LNV E and N within 1e-10 relative at every iteration,
 alpha within 1e-6 for the first 6 iterations (later alpha is a ratio of traces
 that cancel to rounding level), the same iteration count, sampled L blocks with
-||dL|| / ||L|| <= 1e-8 and block-row norms within 1e-8.
+||dL|| / ||L|| <= 1e-8 and block-row norms within 1e-8; where stored, the
+idempotency error ||KS KS - KS|| / ||KS|| of the converged L within 1e-8 relative.
 """
 import json
 import os
@@ -136,3 +137,7 @@ def test_solve_matches_stored_oracle(bsm, case):
     lo = np.array(ls["blocks"]).reshape(lg.shape)
     assert np.linalg.norm(lg - lo) <= 1e-8 * np.linalg.norm(lo)
     np.testing.assert_allclose(_row_norms(L), g["L_row_norms"], rtol=1e-8)
+    if "idempotency_error" in gl:
+        e = lnv.idempotency_error()
+        say(f"[{case}] idempotency error {e:.6e} (oracle {gl['idempotency_error']:.6e})")
+        assert abs(e - gl["idempotency_error"]) <= 1e-8 * gl["idempotency_error"]
