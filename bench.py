@@ -72,9 +72,11 @@ def parse():
                     help="rows per tile for --mode product (0: the library default)")
     ap.add_argument("--column-order", type=int, default=-1, choices=[-1, 0, 1],
                     help="tile column order for --mode product (-1: the library default)")
-    ap.add_argument("--mode", default="solve", choices=["solve", "product"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "product", "classes"],
                     help="product: only the dominant 16 A x 16 A -> 16 A product, --steps launches, plus a "
-                         "2 GiB device copy (for hardware-counter runs and their byte calibration)")
+                         "2 GiB device copy (for hardware-counter runs and their byte calibration); classes: "
+                         "every product class of the 4096-atom solve under each tile setting (rows per "
+                         "tile, direct or transposed plan, column order), --steps launches each")
     return ap.parse_args()
 
 
@@ -121,6 +123,69 @@ def product_mode(args):
 
 
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak
+
+# (r_A, r_B, r_C) of the products in the 4096-atom solve: X = L S, Z G, S U and the like,
+# M(G)'s second product, T = Z S, the Hotelling update, W = X X
+SOLVE_CLASSES = [(10, 6, 16), (8, 10, 18), (6, 16, 10), (18, 8, 10), (8, 6, 14), (14, 8, 8), (16, 16, 16)]
+
+
+def classes_mode(args):
+    """Each product class of the 4096-atom, b = 9 solve on random blocks, timed with HIP events
+    on the library stream under every tile setting; every setting must give the same bits."""
+    import itertools
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    s = synth.si4096_b9()
+    ctx = bsm.Context(0)
+    dev = ctx.device
+    pos = torch.tensor(s.positions, dtype=torch.float64, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    pats, mats = {}, {}
+    for r in sorted({r for c in SOLVE_CLASSES for r in c}):
+        pats[r] = bsm.Pattern(ctx, pos, s.box, float(r), s.b)
+    out = []
+    for ra, rb, rc in SOLVE_CLASSES:
+        for r in (ra, rb):
+            if r not in mats:
+                mats[r] = bsm.Matrix(pats[r], torch.rand((pats[r].nnzb, s.b, s.b), dtype=torch.float64,
+                                                         device=dev, generator=g) - 0.5)
+        A, B, C = mats[ra], mats[rb], bsm.Matrix(pats[rc])
+        flops = bsm.product_flops(pats[ra], pats[rb], pats[rc])
+        ref, rows_out = None, []
+        # the same-pattern class has no transposed plan
+        for rows, tmode, corder in itertools.product((4, 8), (0, 1, 2) if ra != rb else (0,), (0, 1)):
+            ctx.set_rows_per_wave(rows)
+            ctx.set_transposed_plans(tmode)
+            ctx.set_column_order(corder)
+            bsm.multiply_truncate(1.0, A, B, 0.0, C)   # builds the plan
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = C.blocks.clone()
+            elif not torch.equal(ref, C.blocks):
+                raise RuntimeError(f"class {(ra, rb, rc)}: setting {(rows, tmode, corder)} changed the result")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(ctx.stream):
+                e0.record()
+                for _ in range(args.steps):
+                    bsm.multiply_truncate(1.0, A, B, 0.0, C)
+                e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            rows_out.append({"rows": rows, "transposed_plans": tmode, "column_order": corder,
+                             "ms": round(ms, 3), "tflops": round(flops / ms / 1e9, 2)})
+            log(f"[classes] P{ra} x P{rb} -> P{rc}: rows {rows}, transposed {tmode}, column order "
+                f"{corder}: {ms:.3f} ms, {flops / ms / 1e9:.2f} TFLOP/s")
+        default = [r for r in rows_out if r["rows"] == 8 and r["transposed_plans"] == (1 if ra != rb else 0)
+                   and r["column_order"] == 1][0]
+        best = min(rows_out, key=lambda r: r["ms"])
+        out.append({"class": [ra, rb, rc], "flops": flops, "default": default, "best": best,
+                    "default_frac": round(default["tflops"] / FP64_PEAK_TFLOPS, 4), "settings": rows_out})
+        del C
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "classes", "workload": "si4096_b9", "steps": args.steps,
+                      "sources_sha256_16": kernel_sources_sha(), "classes": out}), flush=True)
 
 
 def batch_mode(args):
@@ -732,6 +797,9 @@ def main():
         sys.exit(1)
     if args.mode == "product":
         product_mode(args)
+        return
+    if args.mode == "classes":
+        classes_mode(args)
         return
     if args.workload == "batch64":
         batch_mode(args)
