@@ -761,7 +761,7 @@ def kernel_name(st) -> str:
     depth = 3 if v == 3 and g <= 4 else 2   # 8-row ring tiles run 1 entry ahead in both ring variants
     name = {0: f"k_product_sgpr<{b}, {g}>", 1: f"k_product_f64_dpp<{b}, {g}>", 2: f"k_product_wg<{b}>",
             3: f"k_product_ring<{b}, {g}, {depth}>", 4: f"k_product_ring<{b}, {g}, 2>",
-            5: f"k_product_ring<{b}, {g}, 2, 2 waves>"}.get(v, f"variant {v}")
+            5: f"k_product_ring<{b}, {g}, 2, 2 waves>", 6: f"k_product_mfma_f64<{g}>"}.get(v, f"variant {v}")
     return name if p == 0 else name + (" (FP32)" if p == 1 else " (BF16-rounded, FP32)")
 
 

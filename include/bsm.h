@@ -138,8 +138,11 @@ int bsm_ctx_set_rows_per_wave(bsm_ctx ctx, int rows);
  * (A slots of the rows with outputs in that wave's columns, its B slots), a
  * barrier per entry so that both waves copy the same A blocks together (the
  * second copy is served from cache); rows 4 or 8 (2 gives 4); BF16 products at
- * b = 9 use one-wave plans on the matrix cores; -1 = default (4 for b = 4 and 9,
- * with 8 rows per tile, else 0).
+ * b = 9 use one-wave plans on the matrix cores; 6 = the one-wave tiles of 4 with
+ * FP64 products on the matrix cores (v_mfma_f64_16x16x4_f64, b = 9 only, other b
+ * take 4; rows 4 or 8; direct plans; FP32 and BF16 products take 4), a measured
+ * alternative that multiplies every block pair of its 16 x 16 tiles; -1 = default
+ * (4 for b = 4 and 9, with 8 rows per tile, else 0).
  * Variants 1 to 4 multiply absent (k, j) blocks by zero instead of skipping
  * them, so a non-finite block of A can make other blocks of its output row
  * non-finite.  Clears cached plans (a bsm_batch made before keeps pointers to

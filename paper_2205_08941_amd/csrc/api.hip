@@ -235,7 +235,7 @@ int bsm_ctx_set_product_variant(bsm_ctx ctx, int variant)
 {
     BSM_API_BEGIN
     BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
-    BSM_REQUIRE(variant >= -1 && variant <= 5, BSM_EINVAL, "variant must be -1 .. 5");
+    BSM_REQUIRE(variant >= -1 && variant <= 6, BSM_EINVAL, "variant must be -1 .. 6");
     BSM_HIP_TRY(hipStreamSynchronize(ctx->c.stream));
     ctx->c.retire_profile([](const Plan *) { return true; });
     ctx->c.plans.clear();

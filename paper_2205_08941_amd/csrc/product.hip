@@ -102,6 +102,21 @@ __global__ __launch_bounds__(64 * W) void k_product_ring(
                                       (lds_char_t *)ring + w * kRing, a_bytes, b_bytes);
 }
 
+// FP64 matrix-core tiles (b = 9, G-row wave tiles, variant 6), one per one-wave workgroup.
+template <int G, bool BUF>
+__global__ __launch_bounds__(64) void k_product_mfma_f64(
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
+    const double *__restrict__ vB, const double *__restrict__ zblk, double *__restrict__ vC, double alpha,
+    double beta, unsigned a_bytes, unsigned b_bytes)
+{
+    __shared__ __attribute__((aligned(16))) char ring[2 * RingEntry<9, G, double>::kBytes];
+    const int64_t t = logical_workgroup(nwg_padded);
+    if (t >= ntiles) return;
+    tile_mfma_f64<G, BUF>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta, (lds_char_t *)ring, a_bytes,
+                          b_bytes);
+}
+
 // ---------------------------------------------------------------- operand rounding
 // FP64 -> FP32 (round to nearest even); for BF16, the FP32 value rounded again
 // to 8 significant bits (nearest even, Inf kept, NaN kept quiet), stored as FP32.
@@ -528,10 +543,36 @@ void launch_ring(hipStream_t st, const Plan *plan, const T *A, const T *Bm, doub
     launch_ring_t<B, G, D, T, W, 0>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes);
 }
 
+template <int G>
+void launch_mfma_f64(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
+                     double beta, const double *zblk, int64_t a_bytes, int64_t b_bytes)
+{
+    const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
+    const bool buf = a_bytes <= (int64_t)kBufMaxBytes && b_bytes <= (int64_t)kBufMaxBytes;
+    if (buf)
+        k_product_mfma_f64<G, true><<<(unsigned)nwg_padded, 64, 0, st>>>(
+            plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+            plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta, (unsigned)a_bytes, (unsigned)b_bytes);
+    else
+        k_product_mfma_f64<G, false><<<(unsigned)nwg_padded, 64, 0, st>>>(
+            plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+            plan->ent.as<int>(), A, Bm, zblk, C, alpha, beta, 0u, 0u);
+}
+
 template <int B>
 void launch_b(hipStream_t st, const Plan *plan, const double *A, const double *Bm, double *C, double alpha,
               double beta, const double *zblk, int64_t a_bytes, int64_t b_bytes)
 {
+    if constexpr (B == 9) {
+        if (plan->variant == 6) {   // FP64 matrix cores, direct one-wave plans of 4 or 8 rows
+            if (plan->transposed) throw Error{BSM_EINVAL, "variant 6 takes direct plans"};
+            switch (plan->G) {
+                case 4: launch_mfma_f64<4>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                case 8: launch_mfma_f64<8>(st, plan, A, Bm, C, alpha, beta, zblk, a_bytes, b_bytes); return;
+                default: throw Error{BSM_EINVAL, "variant 6 takes 4 or 8 rows per tile"};
+            }
+        }
+    }
     if constexpr (B == 9 || B == 4) {
         if (plan->variant == 5) {   // LDS rings, tiles shared by two waves
             switch (plan->G) {
@@ -757,6 +798,7 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     }
     BSM_REQUIRE(prec == BSM_F32 || prec == BSM_BF16, BSM_EINVAL, "precision must be F64, F32 or BF16");
     if (plan->G > 8) plan = get_plan_kind(ctx, PA, PB, PC, 0, default_rows_per_wave(PC->b));   // wave tiles
+    if (plan->variant == 6) plan = get_plan_kind(ctx, PA, PB, PC, 4, plan->G);   // reduced precision: the ring
     if (prec == BSM_BF16 && PC->b == 9 && (plan->variant == 5 || plan->transposed))
         plan = get_plan_kind(ctx, PA, PB, PC, 4, plan->G);   // the matrix cores take direct one-wave tiles
     if (plan->ntiles == 0) return;
@@ -864,11 +906,12 @@ Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B
 Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C)
 {
     int variant = ctx->product_variant >= 0 ? ctx->product_variant : default_variant(C->b);
+    if (variant == 6 && C->b != 9) variant = 4;   // the FP64 matrix-core tiles are for b = 9
     if (variant >= 2 && C->b != 9 && C->b != 4) variant = 0;
     int G = variant == 2 ? kMaxRows : (ctx->rows_per_wave > 0 ? ctx->rows_per_wave : default_rows_per_wave(C->b));
-    if ((variant == 4 || variant == 5) && (C->b == 4 || C->b == 9) && ctx->rows_per_wave == 0)
+    if ((variant == 4 || variant == 5 || variant == 6) && (C->b == 4 || C->b == 9) && ctx->rows_per_wave == 0)
         G = 8;   // measured best for the ring
-    if (variant == 5 && G < 4) G = 4;   // two-wave tiles take 4 or 8 rows
+    if ((variant == 5 || variant == 6) && G < 4) G = 4;   // two-wave and matrix-core tiles take 4 or 8 rows
     return get_plan_kind(ctx, A, B, C, variant, G, true);
 }
 

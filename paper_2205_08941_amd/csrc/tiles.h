@@ -754,6 +754,171 @@ __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, co
     }
 }
 
+// ---------------------------------------------------------------- FP64 matrix-core tiles (b = 9)
+// The ring tiles' FP64 product on the matrix cores (v_mfma_f64_16x16x4_f64), kept
+// as a measured alternative to the VALU tile: the same plan (G = 4 or 8 rows x 7
+// columns), the same two-slot LDS ring of FP64 blocks as stored, one entry ahead.
+// The tile's 9 G output rows are ceil(9 G / 16) MFMA row tiles, its 63 columns 4
+// column tiles; an entry's 9-long contraction is three K = 4 steps (12, the last 3
+// zero).  A lane's operands of step s are element (r, 4 s + g) of the A rows and
+// (4 s + g, c) of the B columns (r, c: its row and column within the row and column
+// tile, g = lane / 16); a row tile whose rows all lack an A block in the entry is
+// skipped.  The matrix core multiplies every block pair of a row tile, absent B
+// blocks (staged from the zero block) included: dense 16 x 16 tiles over the
+// lens-shaped triple set.  Sums are FP64, in the matrix core's order.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+template <int G, bool BUF = false>
+__device__ __attribute__((always_inline)) inline void tile_mfma_f64(
+    int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg, const int *__restrict__ ent,
+    const double *__restrict__ vA, const double *__restrict__ vB, const double *__restrict__ zblk,
+    double *__restrict__ vC, double alpha, double beta, lds_char_t *ring, unsigned a_bytes = 0,
+    unsigned b_bytes = 0)
+{
+    using RE = RingEntry<9, G, double>;
+    constexpr int B = 9, JT = 7, BB = 81, D = 2;
+    constexpr int ROWS = 9 * G, RT = (ROWS + 15) / 16;
+    constexpr int HS = G + G * JT, ES = G + JT;
+    constexpr int NB = RE::kBlocks, DW = RE::kDwords, IPB = RE::kInstPerBlock, NI = RE::kInst;
+    static_assert(NB == ES, "one ring block per entry slot");
+    const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
+    const int *h = hdr + tile * HS;
+
+    const int64_t e0 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile] >> 32)) << 32);
+    const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
+    const int n = (int)(e1 - e0);   // even
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES);
+
+    // element offsets (doubles) of this lane's operand rows / columns inside a slot, -1: padding
+    int aoff[RT], boff[4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        const int r = 16 * t + l16;
+        aoff[t] = r < ROWS ? (r / 9) * BB + (r % 9) * B : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int cc = 16 * u + l16;
+        boff[u] = cc < 63 ? (G + cc / 9) * BB + cc % 9 : -1;
+    }
+    f64x4_t acc[RT][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+
+    const int lane4 = 4 * lane;
+    auto load_slots = [&](int q, int (&sl)[NB]) {
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) sl[blk] = entu[(int64_t)q * ES + blk];
+    };
+    const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc((void *)vA, 0, (int)a_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc((void *)vB, 0, (int)b_bytes, 0x00020000);
+    auto issue = [&](auto P, const int (&sl)[NB], int (&asl)[G]) {
+        lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
+#pragma unroll
+        for (int a = 0; a < G; ++a) asl[a] = sl[a];
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) {
+            lds_void_t *l = (lds_void_t *)(slot + blk * (BB * 8));
+            if constexpr (BUF) {
+                const unsigned vo = (unsigned)sl[blk] * (unsigned)(BB * 8) + (unsigned)lane4;
+                dma_block_buf<IPB, DW>(blk < G ? rsA : rsB, vo, l, lane, std::make_integer_sequence<int, IPB>{});
+            } else {
+                const uint64_t real = (uint64_t)(blk < G ? vA : vB) + (uint64_t)((int64_t)sl[blk] * (BB * 8));
+                const uint64_t neg = (uint64_t)(int64_t)(sl[blk] >> 31);
+                const char *gp = reinterpret_cast<const char *>((real & ~neg) | ((uint64_t)zblk & neg)) + lane4;
+                dma_block<IPB, DW>(gp, l, lane, std::make_integer_sequence<int, IPB>{});
+            }
+        }
+    };
+    auto compute = [&](auto P, const int (&as)[G]) {
+        lds_const_t<double> *slot = (lds_const_t<double> *)(ring + decltype(P)::value * RE::kBytes);
+        bool tact[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            bool any = false;
+#pragma unroll
+            for (int a = 0; a < G; ++a)
+                if (9 * a < 16 * t + 16 && 9 * a + 9 > 16 * t) any |= as[a] >= 0;
+            tact[t] = any;
+        }
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int k = 4 * s + g;
+            const bool kok = k < B;
+            double av[RT], bv[4];
+            // padding rows / columns and k >= 9 read element 0 of the slot and use 0
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const bool ok = kok && aoff[t] >= 0;
+                const double v = slot[ok ? aoff[t] + k : 0];
+                av[t] = ok ? v : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = kok && boff[u] >= 0;
+                const double v = slot[ok ? boff[u] + k * B : 0];
+                bv[u] = ok ? v : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                if (!tact[t]) continue;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[u], acc[t][u], 0, 0, 0);
+            }
+        }
+    };
+
+    // two ring positions; each step copies the entry one ahead (past the tile's end:
+    // the next tile's entries or the plan's spare entries, in bounds, never multiplied)
+    int asl[D][G];
+    int sbuf[D][NB];
+    if (n > 0) {
+        load_slots(0, sbuf[0]);
+        load_slots(1, sbuf[1]);
+        issue(std::integral_constant<int, 0>{}, sbuf[0], asl[0]);
+    }
+    for (int q0 = 0; q0 < n; q0 += D) {
+        auto step = [&](auto R) {
+            constexpr int r = decltype(R)::value;
+            constexpr int pn = (r + 1) % D;
+            load_slots(q0 + r + D, sbuf[r]);
+            __builtin_amdgcn_sched_barrier(0);
+            issue(std::integral_constant<int, pn>{}, sbuf[pn], asl[pn]);
+            wait_vmcnt<NI < 63 ? NI : 63>();
+            compute(std::integral_constant<int, r>{}, asl[r]);
+        };
+        step(std::integral_constant<int, 0>{});
+        step(std::integral_constant<int, 1>{});
+    }
+    wait_vmcnt<0>();
+
+    // the FP64 16 x 16 result: lane holds rows 16 t + g + 4 i of column 16 u + l16 of output tile (t, u)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int cc = 16 * u + l16;
+        if (cc >= 63) continue;
+        const int jj = cc / 9, q = cc % 9;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * t + g + 4 * i;
+                if (r >= ROWS) continue;
+                const int a = r / 9, p = r % 9;
+                const int cs = h[G + a * JT + jj];
+                if (cs < 0) continue;
+                double *cp = vC + (int64_t)cs * BB + p * B + q;
+                *cp = beta == 0.0 ? alpha * acc[t][u][i] : scale_add(alpha, acc[t][u][i], beta, *cp);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- BF16 matrix-core tiles (b = 9)
 // The same tiles (G = 4 or 8 rows x 7 columns of 9 x 9 blocks) computed on the
 // matrix cores with v_mfma_f32_16x16x32_bf16.  Operands are pre-packed in BF16: every

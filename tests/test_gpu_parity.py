@@ -160,11 +160,13 @@ def test_product_parity(bsm, ctx, b):
                                                   (1, 2, "si256_disp"), (1, 4, "si256_disp"), (2, 0, "si256_disp"),
                                                   (2, 0, "si216_disp"), (3, 4, "si256_disp"), (3, 2, "si216_disp"),
                                                   (4, 4, "si216_disp"), (4, 2, "si256_disp"), (4, 8, "si216_disp"),
-                                                  (5, 8, "si216_disp"), (5, 4, "si256_disp"), (5, 2, "si216_disp")])
+                                                  (5, 8, "si216_disp"), (5, 4, "si256_disp"), (5, 2, "si216_disp"),
+                                                  (6, 8, "si216_disp"), (6, 4, "si256_disp")])
 @pytest.mark.parametrize("b", [4, 9])
 def test_product_kernel_variants(bsm, b, variant, rows, system):
     """Every product kernel variant and rows-per-wave choice gives the oracle's result
-    (216 atoms: the last 16-row workgroup tile is half empty)."""
+    (216 atoms: the last 16-row workgroup tile is half empty; variant 6, the FP64
+    matrix-core tiles, runs for b = 9 and falls back to the ring for b = 4)."""
     ctx = bsm.Context(0)
     ctx.set_product_variant(variant)
     ctx.set_rows_per_wave(rows)
@@ -184,7 +186,7 @@ def test_product_kernel_variants(bsm, b, variant, rows, system):
     ctx.close()
 
 
-@pytest.mark.parametrize("variant,rows", [(1, 4), (4, 4), (4, 8), (4, 2), (2, 0), (5, 8), (5, 4)])
+@pytest.mark.parametrize("variant,rows", [(1, 4), (4, 4), (4, 8), (4, 2), (2, 0), (5, 8), (5, 4), (6, 8), (6, 4)])
 @pytest.mark.parametrize("b", [4, 9])
 def test_product_degenerate_cases(bsm, b, variant, rows):
     """One atom (one tile, one entry padded to two); diagonal-only operands into a
