@@ -709,7 +709,7 @@ def cpu_baseline(args):
            "sample": f"output block-rows 0..{nrows - 1} of {P.natoms} of the {rx:g} A x {rx:g} A -> {rx:g} A "
                      f"product (the class holding ~90% of LNV flops), random FP64 blocks, "
                      f"{flops / 1e9:.1f} GFLOP in {dt:.1f} s",
-           "cpu": host_cpu(),
+           "cpu": host_cpu(), "nproc": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0)),
            "w_class_product_s_est": round(dt * float(tri.sum()) / float(tri[:nrows].sum()), 2)}
     g = stored_oracle_solve(args.workload)
     if g is not None:
