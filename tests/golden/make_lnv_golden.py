@@ -111,9 +111,10 @@ class ProductCache:
         self.n = 0
         self.saved_s = 0.0      # original compute time of the products loaded
         self.load_s = 0.0       # time spent loading them
+        self.save_s = 0.0       # time spent writing the computed ones
 
     def stage(self, path):
-        self.dir, self.n, self.saved_s, self.load_s = path, 0, 0.0, 0.0
+        self.dir, self.n, self.saved_s, self.load_s, self.save_s = path, 0, 0.0, 0.0, 0.0
         if path:
             os.makedirs(path, exist_ok=True)
 
@@ -143,11 +144,13 @@ class ProductCache:
         with open(base + ".tmp.json", "w") as f:
             json.dump({"s": dt, "nnz": int(pattern.nnz), "prec": prec}, f)
         os.replace(base + ".tmp.json", base + ".json")
+        self.save_s += time.perf_counter() - t0 - dt
         return C
 
     def credit(self):
-        """Seconds the loaded products took when computed, less the time spent loading them."""
-        return self.saved_s - self.load_s
+        """Seconds the loaded products took when computed, less the time spent loading them
+        and saving the others: what the stage would have taken without checkpoints."""
+        return self.saved_s - self.load_s - self.save_s
 
 
 def run(name, ckdir=None):
