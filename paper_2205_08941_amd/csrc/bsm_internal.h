@@ -170,7 +170,8 @@ const bsm_pattern_s *derived_pattern_cached(const bsm_pattern_s *p, double cutof
 void destroy_pattern(bsm_pattern_s *p);
 Plan *get_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C);
 // A plan of a given kernel variant (0: SGPR, 1: DPP wave tiles, 2: workgroup tiles, 3 and 4: LDS-DMA
-// rings, 5: rings with tiles shared by two waves) and rows per tile.
+// rings, 5: rings with tiles shared by two waves, 6: ring tiles on the FP64 matrix cores) and rows
+// per tile; transposed plans only where allowed (variant 4 launches).
 Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C,
                     int variant, int G, bool allow_transposed = false);
 
