@@ -50,7 +50,7 @@ def parse():
                          "truncated S^-1/2 and S^1/2 of the 4096-atom overlap (coupled Newton-Schulz); forces: "
                          "forces of a converged 4096-atom displaced frame; contract: the 4096-atom system "
                          "contracted to 4 on-site support functions per atom and solved, against the 9-orbital solve")
-    ap.add_argument("--guess-train", type=int, default=64, help="training frames of the guess workload")
+    ap.add_argument("--guess-train", type=int, default=48, help="training frames of the guess workload")
     ap.add_argument("--guess-train-cells", type=int, default=8,
                     help="cells per side of the guess training frames (8: 4096 atoms)")
     ap.add_argument("--guess-sample-frac", type=float, default=0.25,
@@ -653,15 +653,38 @@ def guess_mode(args):
         log(f"[guess] {f.sys.natoms} atoms: plain {p['hotelling']} + {p['lnv']} in {p['seconds']:.2f} s; learned "
             f"{g['hotelling']} + {g['lnv']} in {g['seconds']:.2f} s; dE {g['E'] - p['E']:.2e} Ha")
         natoms = f.sys.natoms
+        both = None
+        if natoms <= 4096:
+            # the two extensions together: the mixed-precision schedule of the si4096_b9_mixed
+            # workload (BF16 matrix-core products until the energy rises, FP32 to |dE| < 1e-4 Ha,
+            # 3 FP64 steps), from the plain and from the learned start
+            sched = [(bsm.BF16, 30, 0.0, True), (bsm.F32, 60, 1e-4, True), (bsm.F64, 3, 0.0, False)]
+            f.solve_plain(tol_E=args.tol_e, schedule=sched)     # warm-up: BF16 plans and scratch
+            pm = f.solve_plain(tol_E=args.tol_e, schedule=sched)
+            gm = f.solve_guess(netZ, netL, tol_E=args.tol_e, precision=bsm.BF16, schedule=sched)
+            both = {"schedule": "BF16 products until E rises, FP32 to |dE| < 1e-4 Ha, 3 FP64 steps",
+                    "plain": pm, "learned": gm,
+                    "dE_per_atom_Ha_vs_fp64_plain": {"plain": abs(pm["E"] - p["E"]) / natoms,
+                                                    "learned": abs(gm["E"] - p["E"]) / natoms},
+                    "speedup_vs_fp64_plain": {"plain": round(p["seconds"] / pm["seconds"], 3),
+                                              "learned": round(p["seconds"] / gm["seconds"], 3)}}
+            log(f"[guess] {natoms} atoms, BF16 -> FP32 -> 3 x FP64: plain {pm['seconds']:.2f} s, learned {gm['seconds']:.2f} s; "
+                f"dE/N {both['dE_per_atom_Ha_vs_fp64_plain']['plain']:.2e} / "
+                f"{both['dE_per_atom_Ha_vs_fp64_plain']['learned']:.2e} Ha")
         f.close()
         del f
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        return dict(natoms=natoms, plain=p, learned=g, dE_per_atom_Ha=abs(g["E"] - p["E"]) / natoms,
-                    speedup_vs_plain=round(p["seconds"] / g["seconds"], 3), state_released_per_solve=fresh)
+        out = dict(natoms=natoms, plain=p, learned=g, dE_per_atom_Ha=abs(g["E"] - p["E"]) / natoms,
+                   speedup_vs_plain=round(p["seconds"] / g["seconds"], 3), state_released_per_solve=fresh)
+        if both is not None:
+            out["mixed_precision"] = both
+        return out
 
     results = {}
-    for n in sorted({nt, args.guess_cells}):
+    # the large frame first: it needs nearly all device memory, and the smaller frame's
+    # reduced-precision products leave their operand scratch allocated in the context
+    for n in sorted({nt, args.guess_cells}, reverse=True):
         try:
             results[8 * n ** 3] = compare(n, 20000)
         except Exception as e:   # e.g. device memory: reported, not hidden

@@ -63,15 +63,25 @@ class Frame:
                 return it, res
         raise RuntimeError(f"LNV did not converge in {max_iter} steps")
 
+    def run_schedule(self, schedule):
+        """LNV from the current start through a precision schedule (bsm.LNV.solve stages);
+        returns (steps, result dict)."""
+        r = self.lnv.solve(schedule)
+        if r["status"] != 0 or not r["converged"]:
+            raise RuntimeError(f"LNV schedule ended with status {r['status']}, converged {r['converged']}")
+        return sum(r["iterations"]), r
+
     def release_state(self):
         """Free the LNV solver state (its matrices return to the allocator): for systems whose
         state and Hotelling's temporaries do not fit on the device together."""
         self.close()
         torch.cuda.empty_cache()
 
-    def solve_plain(self, tol_E: float = 1e-8, max_iter: int = 300, fresh_state: bool = False) -> dict:
+    def solve_plain(self, tol_E: float = 1e-8, max_iter: int = 300, fresh_state: bool = False,
+                    schedule=None) -> dict:
         """Hotelling from I / rho, LNV from c mask_L(Z); keeps the plain starts for targets.
-        fresh_state: release the previous solve's LNV state before Hotelling runs."""
+        fresh_state: release the previous solve's LNV state before Hotelling runs.
+        schedule: LNV precision stages (bsm.LNV.solve) instead of FP64 steps to tol_E."""
         if fresh_state:
             self.release_state()
         t = time.perf_counter()
@@ -79,15 +89,21 @@ class Frame:
         lnv = self._lnv(tol_E)
         lnv.reset(init_from_z=True)
         self.L_plain = B.Matrix(self.PL, self.L.blocks.clone())
-        steps, res = self.iterate(max_iter, tol_E)
+        if schedule is None:
+            steps, res = self.iterate(max_iter, tol_E)
+            E, N = res.E, res.N
+        else:
+            steps, r = self.run_schedule(schedule)
+            E, N = r["E"], r["N"]
         torch.cuda.synchronize()
         self.alpha = hr.alpha
-        return dict(hotelling=hr.iterations, lnv=steps, E=res.E, N=res.N, seconds=time.perf_counter() - t)
+        return dict(hotelling=hr.iterations, lnv=steps, E=E, N=N, seconds=time.perf_counter() - t)
 
     def solve_guess(self, netZ: "GuessNet", netL: "GuessNet", tol_E: float = 1e-8, max_iter: int = 300,
-                    precision: int = B.BF16, n_tol: float = 0.01, fresh_state: bool = False) -> dict:
+                    precision: int = B.BF16, n_tol: float = 0.01, fresh_state: bool = False,
+                    schedule=None) -> dict:
         """Hotelling and LNV from the networks' corrected starts (each guarded by the plain one).
-        fresh_state: as in solve_plain."""
+        fresh_state, schedule: as in solve_plain."""
         if fresh_state:
             self.release_state()
         t = time.perf_counter()
@@ -101,10 +117,15 @@ class Frame:
         B.symmetrize(dL)
         lnv = self._lnv(tol_E)
         g = lnv.reset_guess(dL, n_tol=n_tol)
-        steps, res = self.iterate(max_iter, tol_E)
+        if schedule is None:
+            steps, res = self.iterate(max_iter, tol_E)
+            E, N = res.E, res.N
+        else:
+            steps, r = self.run_schedule(schedule)
+            E, N = r["E"], r["N"]
         torch.cuda.synchronize()
         return dict(hotelling=hr.iterations, hotelling_start=hr.start, lnv=steps, accepted=g["accepted"],
-                    E_start_plain=g["E_plain"], E_start_guess=g["E_guess"], E=res.E, N=res.N,
+                    E_start_plain=g["E_plain"], E_start_guess=g["E_guess"], E=E, N=N,
                     seconds=time.perf_counter() - t)
 
     def samples(self, scale_Z: float, scale_L: float):
