@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--workload", default="si4096_b9",
                     choices=["si4096_b9", "si64_b4", "batch64", "si4096_b9_mixed", "guess", "invsqrt", "forces",
                              "contract"],
-                    help="batch64: 64 uneven systems (512-4096 atoms, b = 4 and 9), the 16 A x 16 A -> 16 A "
+                    help="si64_b4: 64 atoms, 4 orbitals: one L S L product, 10 Hotelling steps and 20 LNV "
+                         "iterations, the oracle doing the same; batch64: 64 uneven systems (512-4096 atoms, b = 4 and 9), the 16 A x 16 A -> 16 A "
                          "product of each, per-product launches against one tuned persistent launch; "
                          "si4096_b9_mixed: the solve with BF16 then FP32 products and 3 FP64 steps against "
                          "the FP64 solve; guess: networks trained on 4096-atom displaced frames, held-out 4096- and 32768-atom "
@@ -127,6 +128,85 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak
 # (r_A, r_B, r_C) of the products in the 4096-atom solve: X = L S, Z G, S U and the like,
 # M(G)'s second product, T = Z S, the Hotelling update, W = X X
 SOLVE_CLASSES = [(10, 6, 16), (8, 10, 18), (6, 16, 10), (18, 8, 10), (8, 6, 14), (14, 8, 8), (16, 16, 16)]
+
+
+def small_mode(args):
+    """The 64-atom, 4-orbital system: one L S L product (L S on P(r_L + r_S), then times L on
+    P(2 r_L + r_S)), 10 Hotelling steps and 20 LNV iterations from L0 = c mask_L(Z)."""
+    import torch
+    import synth
+    import paper_2205_08941_amd as bsm
+    s = synth.si64_b4()
+    cut = s.cutoffs
+    ctx = bsm.Context(0)
+    pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
+    PS = bsm.Pattern(ctx, pos, s.box, cut["S"], s.b)
+    PZ = bsm.Pattern(ctx, pos, s.box, cut["Z"], s.b)
+    PL = bsm.Pattern(ctx, pos, s.box, cut["L"], s.b)
+    PX = bsm.Pattern(ctx, pos, s.box, cut["L"] + cut["S"], s.b)
+    PK = bsm.Pattern(ctx, pos, s.box, 2 * cut["L"] + cut["S"], s.b)
+    S, H, Z, L = bsm.Matrix(PS), bsm.Matrix(PS), bsm.Matrix(PZ), bsm.Matrix(PL)
+    X, K = bsm.Matrix(PX), bsm.Matrix(PK)
+    bsm.fill_blocks(S, s.S.rows, s.S.cols, s.S.blocks)
+    bsm.fill_blocks(H, s.H.rows, s.H.cols, s.H.blocks)
+    lnv = None
+
+    def run():
+        nonlocal lnv
+        hr = bsm.hotelling_inverse(S, Z, max_iter=10, tol=0.0)
+        if lnv is None:
+            lnv = bsm.LNV(S, H, Z, L, s.n_electrons, tol_E=0.0, init_from_z=True)
+        else:
+            lnv.reset(init_from_z=True)
+        bsm.multiply_truncate(1.0, L, S, 0.0, X)
+        bsm.multiply_truncate(1.0, X, L, 0.0, K)
+        res = [lnv.step() for _ in range(20)]
+        torch.cuda.synchronize()
+        return hr, res
+
+    for _ in range(max(args.warmup, 1)):
+        run()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        hr, res = run()
+    dt = (time.perf_counter() - t) / args.steps
+    log(f"[si64_b4] 10 Hotelling steps, L S L, 20 LNV iterations: {dt * 1e3:.2f} ms, E = {res[-1].E:.10f}")
+    out = {"metric": "s per 64-atom 4-orb L S L product + 10 Hotelling steps + 20 LNV iterations",
+           "value": round(dt, 6), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": max(args.warmup, 1),
+           "ms_per_step": dt * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "si64_b4: 64 atoms (2 x 2 x 2 cells), 4 orbitals, S = H = 6, L = Z = 8 A",
+                      "natoms": s.natoms, "orbitals_per_atom": s.b},
+           "hotelling_residuals": [hr.residuals[0], hr.residuals[-1]],
+           "E_Ha": [r.E for r in res], "N": [r.N for r in res]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = small_cpu_baseline(s, out["E_Ha"])
+    print(json.dumps(out), flush=True)
+
+
+def small_cpu_baseline(s, E_gpu):
+    """The oracle doing the same work (10 Hotelling steps, L S L, 20 LNV iterations), timed."""
+    import numpy as np
+    import oracle as O
+    cut = s.cutoffs
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    t = time.perf_counter()
+    PS = O.create_pattern(s.positions, s.box, cut["S"])
+    PZ = O.create_pattern(s.positions, s.box, cut["Z"])
+    PL = O.create_pattern(s.positions, s.box, cut["L"])
+    PX = O.create_pattern(s.positions, s.box, cut["L"] + cut["S"])
+    PK = O.create_pattern(s.positions, s.box, 2 * cut["L"] + cut["S"])
+    S = O.from_blocks(PS, s.b, s.S.rows, s.S.cols, s.S.blocks)
+    H = O.from_blocks(PS, s.b, s.H.rows, s.H.cols, s.H.blocks)
+    hr = O.hotelling_inverse(S, PZ, max_iter=10, tol=0.0)
+    st = O.lnv_init(S, H, hr.Z, PL, s.n_electrons, tol_E=0.0)
+    O.product(O.product(st.L, S, PX), st.L, PK)
+    E = [O.lnv_step(st).E for _ in range(20)]
+    dt = time.perf_counter() - t
+    rel = float(np.max(np.abs(np.array(E) - np.array(E_gpu)) / np.abs(np.array(E))))
+    return {"value": round(dt, 3), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": "the whole workload (patterns, 10 Hotelling steps, L S L, 20 LNV iterations)",
+            "cpu": host_cpu(), "max_rel_dE_per_iteration_vs_gpu": rel}
 
 
 def classes_mode(args):
@@ -826,6 +906,9 @@ def main():
         return
     if args.workload == "batch64":
         batch_mode(args)
+        return
+    if args.workload == "si64_b4":
+        small_mode(args)
         return
     if args.workload == "si4096_b9_mixed":
         mixed_mode(args)
