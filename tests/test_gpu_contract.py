@@ -60,10 +60,12 @@ def test_contract_parity(bsm, cells, kind):
     ctx.close()
 
 
-def test_contracted_lnv_parity(bsm):
-    # 64 atoms, 9 orbitals contracted to 4 on-site support functions; Hotelling (10 steps)
-    # and 10 LNV steps of the contracted system on both sides
-    s = synth.make_system("c", 2, 9, synth.SMALL_CUTOFFS, 5)
+@pytest.mark.parametrize("cells,cutoffs,steps", [(2, synth.SMALL_CUTOFFS, 10), ((4, 4, 4), synth.BIG_CUTOFFS, 4)])
+def test_contracted_lnv_parity(bsm, cells, cutoffs, steps):
+    # 9 orbitals contracted to 4 on-site support functions; Hotelling (10 steps) and LNV steps
+    # of the contracted system on both sides: 64 atoms, and 512 atoms on the 6/8/10 A cutoffs
+    # (L, S^-1 and the overlap truncated)
+    s = synth.make_system("c", cells, 9, cutoffs, 5)
     coef = onsite_coef(s, 4)
     ctx = bsm.Context(0)
     pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
@@ -79,13 +81,13 @@ def test_contracted_lnv_parity(bsm):
     L = bsm.Matrix(bsm.Pattern(ctx, pos, s.box, s.cutoffs["L"], 4))
     bsm.hotelling_inverse(Sc, Z, max_iter=10, tol=0.0)
     lnv = bsm.LNV(Sc, Hc, Z, L, s.n_electrons)
-    g = [lnv.step().E for _ in range(10)]
+    g = [lnv.step().E for _ in range(steps)]
     oP = O.create_pattern(s.positions, s.box, s.cutoffs["S"])
     oS = O.contract(O.from_blocks(oP, 9, s.S.rows, s.S.cols, s.S.blocks), coef)
     oH = O.contract(O.from_blocks(oP, 9, s.H.rows, s.H.cols, s.H.blocks), coef)
     oZ = O.hotelling_inverse(oS, O.create_pattern(s.positions, s.box, s.cutoffs["Z"]), max_iter=10, tol=0.0).Z
     st = O.lnv_init(oS, oH, oZ, O.create_pattern(s.positions, s.box, s.cutoffs["L"]), s.n_electrons)
-    o = [O.lnv_step(st).E for _ in range(10)]
+    o = [O.lnv_step(st).E for _ in range(steps)]
     say(f"contracted LNV: E {g[-1]:.10f} (oracle {o[-1]:.10f})")
     np.testing.assert_allclose(g, o, rtol=1e-10)
     ctx.close()

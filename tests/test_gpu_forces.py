@@ -62,18 +62,21 @@ class GpuFrame:
         return lnv, r["E"]
 
 
-@pytest.mark.parametrize("cells,b", [(2, 4), (2, 9), ((3, 3, 3), 4)])
-def test_forces_parity_same_L(bsm, cells, b):
-    # the oracle's converged L and Z loaded into the GPU state: forces within 1e-10 of the
-    # largest component (only summation orders differ)
-    s = synth.make_system("f", cells, b, synth.SMALL_CUTOFFS, 11, derivatives=True, **KW)
+@pytest.mark.parametrize("cells,b,cutoffs,steps", [(2, 4, synth.SMALL_CUTOFFS, 12), (2, 9, synth.SMALL_CUTOFFS, 12),
+                                                   ((3, 3, 3), 4, synth.SMALL_CUTOFFS, 12),
+                                                   ((4, 4, 4), 4, synth.BIG_CUTOFFS, 3)])
+def test_forces_parity_same_L(bsm, cells, b, cutoffs, steps):
+    # the oracle's L (after `steps` LNV steps) and Z loaded into the GPU state: forces within
+    # 1e-10 of the largest component (only summation orders differ); 512 atoms on the 6/8/10 A
+    # cutoffs: L, S^-1 and the overlap are truncated (191, 99 and 47 of 512 columns)
+    s = synth.make_system("f", cells, b, cutoffs, 11, derivatives=True, **KW)
     say(f"forces parity {s.natoms} atoms b={b}")
     P6 = O.create_pattern(s.positions, s.box, s.cutoffs["S"])
     oS = O.from_blocks(P6, b, s.S.rows, s.S.cols, s.S.blocks)
     oH = O.from_blocks(P6, b, s.H.rows, s.H.cols, s.H.blocks)
     oZ = O.hotelling_inverse(oS, O.create_pattern(s.positions, s.box, s.cutoffs["Z"]), max_iter=100).Z
     st = O.lnv_init(oS, oH, oZ, O.create_pattern(s.positions, s.box, s.cutoffs["L"]), s.n_electrons, tol_E=1e-11)
-    O.lnv_solve(st, [(O.F64, 12, 0.0, False)])   # any L: both sides differentiate at the same point
+    O.lnv_solve(st, [(O.F64, steps, 0.0, False)])   # any L: both sides differentiate at the same point
     Fo = O.lnv_forces(st, [O.from_blocks(P6, b, d.rows, d.cols, d.blocks) for d in s.dS],
                       [O.from_blocks(P6, b, d.rows, d.cols, d.blocks) for d in s.dH])
     ctx = bsm.Context(0)
