@@ -73,6 +73,9 @@ def parse():
                     help="rows per tile for --mode product (0: the library default)")
     ap.add_argument("--column-order", type=int, default=-1, choices=[-1, 0, 1],
                     help="tile column order for --mode product (-1: the library default)")
+    ap.add_argument("--pair", action="store_true",
+                    help="--mode product: the paired launch W = X X, U = Y X (two products sharing B) "
+                         "instead of X X alone")
     ap.add_argument("--mode", default="solve", choices=["solve", "product", "classes"],
                     help="product: only the dominant 16 A x 16 A -> 16 A product, --steps launches, plus a "
                          "2 GiB device copy (for hardware-counter runs and their byte calibration); classes: "
@@ -102,9 +105,18 @@ def product_mode(args):
     C = bsm.Matrix(P)
     flops = bsm.product_flops(P, P, P)
     prec = {"f64": bsm.F64, "f32": bsm.F32, "bf16": bsm.BF16}[args.prec]
+    if args.pair:
+        if prec != bsm.F64:
+            raise SystemExit("--pair runs FP64 products")
+        Y = bsm.Matrix(P, torch.rand((P.nnzb, b, b), dtype=torch.float64, device=ctx.device, generator=g) - 0.5)
+        C2 = bsm.Matrix(P)
+        flops *= 2
     ctx.set_profiling(True)
     for k in range(args.steps):
-        bsm.multiply_truncate_prec(prec, 1.0, X, X, 0.0, C)
+        if args.pair:
+            bsm.multiply_truncate_pair(1.0, X, Y, X, 0.0, C, C2)
+        else:
+            bsm.multiply_truncate_prec(prec, 1.0, X, X, 0.0, C)
         torch.cuda.synchronize()
         log(f"[product] launch {k}")
     st = ctx.product_stats()[0]
@@ -114,12 +126,13 @@ def product_mode(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     ms = st["ms"] / st["launches"]
-    print(json.dumps({"mode": "product", "precision": args.prec, "column_order": args.column_order,
+    print(json.dumps({"mode": "product", "pair": args.pair, "precision": args.prec, "column_order": args.column_order,
                       "kernel": kernel_name(st),
                       "sources_sha256_16": kernel_sources_sha(),
                       "flops_per_launch": flops, "avg_ms": ms,
                       "tflops": flops / (ms * 1e-3) / 1e12, "blocks": P.nnzb,
-                      "algorithmic_bytes": 3 * P.nnzb * b * b * 8, "copy_bytes": 2 * src.numel() * 8}),
+                      "algorithmic_bytes": (5 if args.pair else 3) * P.nnzb * b * b * 8,
+                      "copy_bytes": 2 * src.numel() * 8}),
           flush=True)
 
 
@@ -859,6 +872,8 @@ def kernel_sources_sha() -> str:
 
 def kernel_name(st) -> str:
     b, g, v, p = st["b"], st["rows"], st["variant"], st.get("precision", 0)
+    if st.get("products", 1) == 2:
+        return f"k_product_ring_pair<{b}, {2 * g}> (2 products sharing B on one {g}-row plan)"
     if p == 2 and b == 9 and g in (4, 8) and v in (3, 4):
         return f"k_product_mfma_bf16<{g}>"
     depth = 3 if v == 3 and g <= 4 else 2   # 8-row ring tiles run 1 entry ahead in both ring variants
@@ -1027,7 +1042,8 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": measured_traffic(f"k_product_si4096_b9_traffic.json") if s.b == 9 else None,
+            "traffic": (measured_traffic("k_product_pair_si4096_b9_traffic.json" if top.get("products", 1) == 2
+                                         else "k_product_si4096_b9_traffic.json") if s.b == 9 else None),
             "avg_launch_ms": round(avg_ms, 3),
             "launches": top["launches"],
             "flops_per_launch": per_launch_flops,

@@ -116,6 +116,7 @@ typedef struct {
     double ms;           /* summed event time, milliseconds */
     int variant, rows;   /* kernel variant (bsm_ctx_set_product_variant) and rows per tile */
     int precision;       /* BSM_F64, BSM_F32 or BSM_BF16 */
+    int products;        /* products per launch: 1, or 2 for bsm_multiply_truncate_pair */
 } bsm_product_stat;
 
 /* Rows of C per wavefront tile in product plans built from now on: 2, 4 or 8
@@ -233,6 +234,19 @@ int bsm_dot(bsm_ctx ctx, const bsm_matrix *A, const bsm_matrix *B, double *out);
  * blocks alias A's or B's, dtype not F64), BSM_ENOMEM, BSM_EHIP. */
 int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *B,
                           double beta, const bsm_matrix *C);
+
+/* Two truncated products that share their right operand, in one launch:
+ * C <- alpha mask_{P_C}(A B) + beta C and C2 <- alpha mask_{P_C}(A2 B) + beta C2,
+ * with A and A2 on one pattern and C and C2 on one pattern (the same products as
+ * bsm_multiply_truncate, Background).  For b = 4 and 9 with the default kernel
+ * the pair runs as tiles of twice the rows of one 4-row plan: every copied block
+ * of B serves both products, and each element of C and C2 equals, bit for bit,
+ * what bsm_multiply_truncate gives; otherwise the two products run one after the
+ * other.  LNV evaluates W = X X and U = Y X this way.  Asynchronous.  Errors: as
+ * bsm_multiply_truncate, and BSM_EPATTERN when A2 or C2 is not on A's or C's
+ * pattern; BSM_EINVAL when C or C2 aliases an operand or each other. */
+int bsm_multiply_truncate_pair(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *A2,
+                               const bsm_matrix *B, double beta, const bsm_matrix *C, const bsm_matrix *C2);
 /* The same product with every element of A and B first rounded to `precision`:
  * BSM_F32 (round to nearest even) or BSM_BF16 (to FP32, then to 8 significant
  * bits, nearest even); products accumulated in FP32 by fused multiply-adds over

@@ -93,7 +93,7 @@ class _GuessResult(ctypes.Structure):
 class _ProductStat(ctypes.Structure):
     _fields_ = [("natoms", c_int), ("b", c_int), ("cutoff_a", c_double), ("cutoff_b", c_double),
                 ("cutoff_c", c_double), ("launches", c_int64), ("flops", c_double), ("ms", c_double),
-                ("variant", c_int), ("rows", c_int), ("precision", c_int)]
+                ("variant", c_int), ("rows", c_int), ("precision", c_int), ("products", c_int)]
 
 
 class _LNVParams(ctypes.Structure):
@@ -146,6 +146,9 @@ EXPORTS = {
     "bsm_dot": (c_int, [c_void_p, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix), ctypes.POINTER(c_double)]),
     "bsm_multiply_truncate": (c_int, [c_void_p, c_double, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                       c_double, ctypes.POINTER(_Matrix)]),
+    "bsm_multiply_truncate_pair": (c_int, [c_void_p, c_double, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                                           ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix),
+                                           ctypes.POINTER(_Matrix)]),
     "bsm_product_flops": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double)]),
     "bsm_multiply_truncate_prec": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(_Matrix),
                                            ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix)]),
@@ -285,7 +288,7 @@ class Context:
         _check(_lib.bsm_ctx_product_stats(self.handle, arr, n.value, ctypes.byref(n)))
         return [dict(natoms=a.natoms, b=a.b, cutoffs=(a.cutoff_a, a.cutoff_b, a.cutoff_c),
                      launches=a.launches, flops=a.flops, ms=a.ms, variant=a.variant, rows=a.rows,
-                     precision=a.precision) for a in arr[: n.value]]
+                     precision=a.precision, products=a.products) for a in arr[: n.value]]
 
     def _alloc(self, nbytes, user):
         try:
@@ -378,6 +381,14 @@ def fill_blocks(M: Matrix, rows, cols, blocks) -> None:
 
 def multiply_truncate(alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix) -> None:
     _check(_lib.bsm_multiply_truncate(C.pattern.ctx.handle, float(alpha), A.c, B.c, float(beta), C.c))
+
+
+def multiply_truncate_pair(alpha: float, A: Matrix, A2: Matrix, B: Matrix, beta: float, C: Matrix,
+                           C2: Matrix) -> None:
+    """C <- alpha mask(A B) + beta C and C2 <- alpha mask(A2 B) + beta C2 in one launch (A, A2 on one
+    pattern, C, C2 on one pattern)."""
+    _check(_lib.bsm_multiply_truncate_pair(C.pattern.ctx.handle, float(alpha), A.c, A2.c, B.c, float(beta), C.c,
+                                           C2.c))
 
 
 def multiply_truncate_prec(precision: int, alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix) -> None:

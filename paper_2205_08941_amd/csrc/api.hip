@@ -85,7 +85,7 @@ void Context::retire_profile(const std::function<bool(const Plan *)> &pick)
                 (void)hipEventElapsedTime(&ms, r.start, r.stop);
                 auto &acc = retired[prof_key(r)];
                 acc.launches += 1;
-                acc.flops += r.plan->flops;
+                acc.flops += r.plan->flops * r.products;
                 acc.ms += ms;
                 event_pool.push_back(r.start);
                 event_pool.push_back(r.stop);
@@ -309,7 +309,7 @@ int bsm_ctx_product_stats(bsm_ctx ctx, bsm_product_stat *out, int max, int *coun
         BSM_HIP_TRY(hipEventElapsedTime(&ms, r.start, r.stop));
         auto &acc = agg[Context::prof_key(r)];
         acc.launches += 1;
-        acc.flops += r.plan->flops;
+        acc.flops += r.plan->flops * r.products;
         acc.ms += ms;
     }
     std::vector<bsm_product_stat> v;
@@ -323,6 +323,7 @@ int bsm_ctx_product_stats(bsm_ctx ctx, bsm_product_stat *out, int max, int *coun
         s.variant = std::get<5>(kv.first);
         s.rows = std::get<6>(kv.first);
         s.precision = std::get<7>(kv.first);
+        s.products = std::get<8>(kv.first);
         s.launches = kv.second.launches;
         s.flops = kv.second.flops;
         s.ms = kv.second.ms;
@@ -481,6 +482,40 @@ int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const 
     Plan *plan = get_plan(&ctx->c, A->pattern, B->pattern, C->pattern);
     launch_product_f64(&ctx->c, plan, alpha, A->pattern, (const double *)A->blocks, B->pattern,
                        (const double *)B->blocks, beta, C->pattern, (double *)C->blocks);
+    return BSM_OK;
+    BSM_API_END
+}
+
+int bsm_multiply_truncate_pair(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *A2,
+                               const bsm_matrix *B, double beta, const bsm_matrix *C, const bsm_matrix *C2)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
+    check_matrix(A, "A");
+    check_matrix(A2, "A2");
+    check_matrix(B, "B");
+    check_matrix(C, "C");
+    check_matrix(C2, "C2");
+    check_same_shape(A, B);
+    check_same_shape(A, C);
+    BSM_REQUIRE(A2->pattern == A->pattern, BSM_EPATTERN, "A2 must lie on A's pattern");
+    BSM_REQUIRE(C2->pattern == C->pattern, BSM_EPATTERN, "C2 must lie on C's pattern");
+    BSM_REQUIRE(!overlaps(C, A) && !overlaps(C, A2) && !overlaps(C, B) && !overlaps(C2, A) &&
+                    !overlaps(C2, A2) && !overlaps(C2, B) && !overlaps(C, C2),
+                BSM_EINVAL, "C or C2 overlaps an operand or each other");
+    Context *c = &ctx->c;
+    Plan *pair = get_pair_plan(c, A->pattern, B->pattern, C->pattern);
+    if (pair) {
+        launch_product_pair_f64(c, pair, alpha, A->pattern, (const double *)A->blocks, (const double *)A2->blocks,
+                                B->pattern, (const double *)B->blocks, beta, C->pattern, (double *)C->blocks,
+                                (double *)C2->blocks);
+    } else {
+        Plan *plan = get_plan(c, A->pattern, B->pattern, C->pattern);
+        launch_product_f64(c, plan, alpha, A->pattern, (const double *)A->blocks, B->pattern,
+                           (const double *)B->blocks, beta, C->pattern, (double *)C->blocks);
+        launch_product_f64(c, plan, alpha, A->pattern, (const double *)A2->blocks, B->pattern,
+                           (const double *)B->blocks, beta, C->pattern, (double *)C2->blocks);
+    }
     return BSM_OK;
     BSM_API_END
 }

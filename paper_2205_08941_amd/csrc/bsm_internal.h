@@ -105,13 +105,15 @@ class Context {
         const Plan *plan;
         hipEvent_t start, stop;
         int prec;               // BSM_F64, BSM_F32 or BSM_BF16
+        int products = 1;       // 2: a paired launch (two products on one plan)
     };
-    // statistics class: (natoms, b, cutoffs A, B, C, kernel variant, rows per tile, precision)
-    using ProfKey = std::tuple<int, int, double, double, double, int, int, int>;
+    // statistics class: (natoms, b, cutoffs A, B, C, kernel variant, rows per tile, precision,
+    // products per launch)
+    using ProfKey = std::tuple<int, int, double, double, double, int, int, int, int>;
     static ProfKey prof_key(const ProfRec &r)
     {
         return ProfKey(r.plan->natoms, r.plan->b, r.plan->cutoffs[0], r.plan->cutoffs[1], r.plan->cutoffs[2],
-                       r.plan->variant, r.plan->G, r.prec);
+                       r.plan->variant, r.plan->G, r.prec, r.products);
     }
     bool profiling = false;
     std::vector<ProfRec> prof;
@@ -179,6 +181,13 @@ Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B
 void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
                         const double *A, const bsm_pattern_s *PB, const double *B, double beta,
                         const bsm_pattern_s *PC, double *C);
+// The plan of a paired FP64 launch (C = alpha A B + beta C and C2 = alpha A2 B + beta C2, A and A2
+// on PA): direct one-wave ring tiles of 4 rows, the pair run as 8-row tiles; nullptr when the
+// pair cannot run as one launch (b other than 4 and 9, or another kernel variant chosen).
+Plan *get_pair_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC);
+void launch_product_pair_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
+                             const double *A, const double *A2, const bsm_pattern_s *PB, const double *B,
+                             double beta, const bsm_pattern_s *PC, double *C, double *C2);
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
                 Plan *plan, int G, int waves, int transposed = 0);
 // prec BSM_F64: the FP64 product; BSM_F32 / BSM_BF16: operands rounded to that

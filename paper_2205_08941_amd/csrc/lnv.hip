@@ -121,6 +121,19 @@ struct lnv_state_s {
         flops += plan->flops;
     }
     void mul(const Mat &A, const Mat &B, Mat &C) { mul(1.0, A.p, A.d(), B.p, B.d(), 0.0, C.p, C.d()); }
+    // C = A B and C2 = A2 B (A, A2 on one pattern): FP64 pairs share B's copies in one launch
+    // with the same results as two products
+    void mul_pair(const Mat &A, const Mat &A2, const Mat &B, Mat &C, Mat &C2)
+    {
+        Plan *pair = prec == BSM_F64 ? get_pair_plan(c, A.p, B.p, C.p) : nullptr;
+        if (!pair) {
+            mul(A, B, C);
+            mul(A2, B, C2);
+            return;
+        }
+        launch_product_pair_f64(c, pair, 1.0, A.p, A.d(), A2.d(), B.p, B.d(), 0.0, C.p, C.d(), C2.d());
+        flops += 2.0 * pair->flops;
+    }
     void precondition(const Mat &G, Mat &out)
     {
         mul(1.0, PZ, Z, G.p, G.d(), 0.0, ZG.p, ZG.d());
@@ -356,8 +369,7 @@ int lnv_state_s::step(lnv_result *res)
         // ---- evaluate: X = LS, Y = LH, W = XX, U = YX; E, N from traces
         st->mul(1.0, PL, st->L, st->PS, st->S, 0.0, X.p, X.d());
         st->mul(1.0, PL, st->L, st->PH, st->H, 0.0, Y.p, Y.d());
-        st->mul(X, X, W);
-        st->mul(Y, X, U);
+        st->mul_pair(X, Y, X, W, U);                                 // W = X X, U = Y X
         double tr0[4];
         {
             const double *a[2] = {X.d(), W.d()}, *b[2] = {Y.d(), X.d()};   // Tr XY, Tr WY, Tr XX, Tr WX
@@ -535,8 +547,7 @@ extern "C" int lnv_forces(lnv_state *st, const bsm_matrix *dS, const bsm_matrix 
         // chemical potential at the current L (canonical definition), as a step computes it
         st->mul(1.0, PL, st->L, PS, st->S, 0.0, X.p, X.d());
         st->mul(1.0, PL, st->L, PH, st->H, 0.0, Y.p, Y.d());
-        st->mul(X, X, W);
-        st->mul(Y, X, U);
+        st->mul_pair(X, Y, X, W, U);                                 // W = X X, U = Y X
         st->gradients();
         st->precondition(st->GE, st->PE);
         st->precondition(st->GN, st->PN);

@@ -102,6 +102,23 @@ __global__ __launch_bounds__(64 * W) void k_product_ring(
                                       (lds_char_t *)ring + w * kRing, a_bytes, b_bytes);
 }
 
+// Two products sharing B and the patterns (C = A B, C2 = A2 B) on one plan of G / 2
+// rows: one wave tile of G rows per one-wave workgroup, B's copies serving both.
+template <int B, int G, bool BUF>
+__global__ __launch_bounds__(64) void k_product_ring_pair(
+    int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
+    const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
+    const double *__restrict__ vA2, const double *__restrict__ vB, const double *__restrict__ zblk,
+    double *__restrict__ vC, double *__restrict__ vC2, double alpha, double beta, unsigned a_bytes,
+    unsigned a2_bytes, unsigned b_bytes)
+{
+    __shared__ __attribute__((aligned(16))) char ring[2 * RingEntry<B, G, double>::kBytes];
+    const int64_t t = logical_workgroup(nwg_padded);
+    if (t >= ntiles) return;
+    tile_ring<B, G, 2, double, BUF, 1, 0, 2>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta,
+                                             (lds_char_t *)ring, a_bytes, b_bytes, vA2, vC2, a2_bytes);
+}
+
 // FP64 matrix-core tiles (b = 9, G-row wave tiles, variant 6), one per one-wave workgroup.
 template <int G, bool BUF>
 __global__ __launch_bounds__(64) void k_product_mfma_f64(
@@ -781,6 +798,71 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
 #undef X
         default: throw Error{BSM_EINVAL, "b must be in 1..16"};
     }
+    BSM_HIP_TRY(hipGetLastError());
+    if (ctx->profiling) {
+        BSM_HIP_TRY(hipEventRecord(rec.stop, st));
+        ctx->prof.push_back(rec);
+    }
+}
+
+Plan *get_pair_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC)
+{
+    const int b = PC->b;
+    if (b != 4 && b != 9) return nullptr;
+    if (ctx->product_variant >= 0 && ctx->product_variant != 4) return nullptr;
+    // direct 4-row ring plan: 8 rows per paired tile
+    auto it = ctx->plans.find(std::make_tuple(PA->id, PB->id, PC->id, 4, 4, 0));
+    if (it != ctx->plans.end()) return it->second.get();
+    // The 4-row plan is a second plan beside the default one (about 1.3 times its size, 4.9 GB
+    // for the 16 A class at 4096 atoms, eight times that at 32768): built only while free
+    // device memory holds twice that and 8 GB more, else the pair runs as two launches (same
+    // results either way)
+    const Plan *one = get_plan(ctx, PA, PB, PC);
+    const double est = 1.3 * (double)(one->ent.bytes + one->hdr.bytes + one->order.bytes + one->ebeg.bytes);
+    size_t free_b = 0, total_b = 0;
+    BSM_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    if ((double)free_b < 2.0 * est + 8.0 * (1u << 30)) return nullptr;
+    return get_plan_kind(ctx, PA, PB, PC, 4, 4);
+}
+
+namespace {
+template <int B>
+void launch_pair(hipStream_t st, const Plan *plan, const double *A, const double *A2, const double *Bm, double *C,
+                 double *C2, double alpha, double beta, const double *zblk, int64_t a_bytes, int64_t b_bytes)
+{
+    const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
+    const bool buf = a_bytes <= (int64_t)kBufMaxBytes && b_bytes <= (int64_t)kBufMaxBytes;
+    if (buf)
+        k_product_ring_pair<B, 8, true><<<(unsigned)nwg_padded, 64, 0, st>>>(
+            plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+            plan->ent.as<int>(), A, A2, Bm, zblk, C, C2, alpha, beta, (unsigned)a_bytes, (unsigned)a_bytes,
+            (unsigned)b_bytes);
+    else
+        k_product_ring_pair<B, 8, false><<<(unsigned)nwg_padded, 64, 0, st>>>(
+            plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
+            plan->ent.as<int>(), A, A2, Bm, zblk, C, C2, alpha, beta, 0u, 0u, 0u);
+}
+}  // namespace
+
+void launch_product_pair_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
+                             const double *A, const double *A2, const bsm_pattern_s *PB, const double *Bm,
+                             double beta, const bsm_pattern_s *PC, double *C, double *C2)
+{
+    BSM_REQUIRE(plan->variant == 4 && plan->G == 4 && !plan->transposed && (PC->b == 4 || PC->b == 9),
+                BSM_EINVAL, "a paired launch takes a direct 4-row ring plan, b = 4 or 9");
+    if (plan->ntiles == 0) return;
+    hipStream_t st = ctx->stream;
+    Context::ProfRec rec{plan, nullptr, nullptr, BSM_F64, 2};
+    if (ctx->profiling) {
+        rec.start = ctx->take_event();
+        rec.stop = ctx->take_event();
+        BSM_HIP_TRY(hipEventRecord(rec.start, st));
+    }
+    const int64_t ab = 8 * nelems(PA), bb = 8 * nelems(PB);
+    if (PC->b == 9)
+        launch_pair<9>(st, plan, A, A2, Bm, C, C2, alpha, beta, ctx->zero_block.as<double>(), ab, bb);
+    else
+        launch_pair<4>(st, plan, A, A2, Bm, C, C2, alpha, beta, ctx->zero_block.as<double>(), ab, bb);
     BSM_HIP_TRY(hipGetLastError());
     if (ctx->profiling) {
         BSM_HIP_TRY(hipEventRecord(rec.stop, st));

@@ -583,21 +583,30 @@ constexpr unsigned kBufMaxBytes = 0xfffff000u;
 // transposed from the ring and the result is stored transposed, at the slot of
 // (j, i) that the plan's header gives.  Each element sums the same terms in the
 // same order as the direct product.
-template <int B, int G, int D, class T = double, bool BUF = false, int W = 1, int TR = 0>
+// DU = 2: two products that share B and the patterns, C = A B and C2 = A2 B, on
+// one plan of G / 2 rows: the tile's first G / 2 rows multiply A's blocks, the
+// other G / 2 the same slots of A2, and every B block copied serves both.  Each
+// product's elements sum the same terms in the same order as its own launch.
+template <int B, int G, int D, class T = double, bool BUF = false, int W = 1, int TR = 0, int DU = 1>
 __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
                                  const int *__restrict__ ent, const T *__restrict__ vA, const T *__restrict__ vB,
                                  const T *__restrict__ zblk, double *__restrict__ vC, double alpha, double beta,
-                                 lds_char_t *ring, unsigned a_bytes = 0, unsigned b_bytes = 0)
+                                 lds_char_t *ring, unsigned a_bytes = 0, unsigned b_bytes = 0,
+                                 const T *__restrict__ vA2 = nullptr, double *__restrict__ vC2 = nullptr,
+                                 unsigned a2_bytes = 0)
 {
     using RE = RingEntry<B, G, T>;
     static_assert(W == 1 || W == 2, "one or two waves per tile");
     static_assert(TR == 0 || W == 1, "transposed products use one-wave tiles");
+    static_assert(DU == 1 || (DU == 2 && W == 1 && TR == 0 && G % 2 == 0), "paired products: one-wave direct tiles");
     constexpr int ESZ = (int)sizeof(T);
     constexpr int JT = 64 / B;
     constexpr int BB = B * B;
     constexpr int NA = (BB + 15) / 16;
-    constexpr int HS = G + G * JT * W;
-    constexpr int ES = (G + JT) * W;
+    constexpr int GP = G / DU;                 // rows of the plan
+    constexpr int HS = GP + GP * JT * W;
+    constexpr int ES = (GP + JT) * W;
+    constexpr int NS = GP + JT;                // plan slots per entry and wave
     constexpr int NB = RE::kBlocks, DW = RE::kDwords, IPB = RE::kInstPerBlock, NI = RE::kInst;
     const int lane = threadIdx.x & 63;
     const int w = W > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
@@ -610,7 +619,7 @@ __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, co
     bool cact[G];
 #pragma unroll
     for (int a = 0; a < G; ++a) {
-        cs[a] = lane_ok ? h[G + a * JT * W + w * JT + jl] : -1;
+        cs[a] = lane_ok ? h[GP + (a % GP) * JT * W + w * JT + jl] : -1;
         cact[a] = cs[a] >= 0;
     }
     T acc[G][B];
@@ -624,7 +633,7 @@ __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, co
     const int64_t e1 = __builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] & 0xffffffff)) |
                        ((int64_t)__builtin_amdgcn_readfirstlane((int)(ebeg[tile + 1] >> 32)) << 32);
     const int n = (int)(e1 - e0);
-    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES + w * (G + JT));
+    const_as4<int> *entu = (const_as4<int> *)(ent + e0 * ES + w * NS);
 
     // Copy an entry, given its slots, into ring position P; keep its A slots in
     // `asl`.  The DMA's immediate offset advances the global and the LDS address
@@ -633,26 +642,32 @@ __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, co
     // the tile's end these loads read the next tile's entries or the plan's four
     // spare entries, which are not used.
     const int lane4 = 4 * lane;
-    auto load_slots = [&](int q, int (&sl)[NB]) {
+    auto load_slots = [&](int q, int (&sl)[NS]) {
 #pragma unroll
-        for (int blk = 0; blk < NB; ++blk) sl[blk] = entu[(int64_t)q * ES + blk];
+        for (int blk = 0; blk < NS; ++blk) sl[blk] = entu[(int64_t)q * ES + blk];
     };
     const __amdgpu_buffer_rsrc_t rsA = __builtin_amdgcn_make_buffer_rsrc((void *)vA, 0, (int)a_bytes, 0x00020000);
     const __amdgpu_buffer_rsrc_t rsB = __builtin_amdgcn_make_buffer_rsrc((void *)vB, 0, (int)b_bytes, 0x00020000);
-    auto issue = [&](auto P, const int (&sl)[NB], int (&asl)[G]) {
+    const __amdgpu_buffer_rsrc_t rsA2 =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(DU == 2 ? vA2 : vA), 0, (int)(DU == 2 ? a2_bytes : a_bytes), 0x00020000);
+    // ring block blk: A rows (the plan's rows, then for DU = 2 the same slots of A2), then B columns
+    auto issue = [&](auto P, const int (&sl)[NS], int (&asl)[G]) {
         lds_char_t *slot = ring + decltype(P)::value * RE::kBytes;
 #pragma unroll
-        for (int a = 0; a < G; ++a) asl[a] = sl[a];
+        for (int a = 0; a < G; ++a) asl[a] = sl[a % GP];
 #pragma unroll
         for (int blk = 0; blk < NB; ++blk) {
             lds_void_t *l = (lds_void_t *)(slot + blk * (BB * ESZ));
+            const int s_ = blk < G ? sl[blk % GP] : sl[GP + (blk - G)];
             if constexpr (BUF) {
-                const unsigned vo = (unsigned)sl[blk] * (unsigned)(BB * ESZ) + (unsigned)lane4;
-                dma_block_buf<IPB, DW>(blk < G ? rsA : rsB, vo, l, lane, std::make_integer_sequence<int, IPB>{});
+                const unsigned vo = (unsigned)s_ * (unsigned)(BB * ESZ) + (unsigned)lane4;
+                dma_block_buf<IPB, DW>(blk < GP ? rsA : (blk < G ? rsA2 : rsB), vo, l, lane,
+                                       std::make_integer_sequence<int, IPB>{});
             } else {
                 // absent blocks (slot -1) copy the zero block; selected with masks, not a branch
-                const uint64_t real = (uint64_t)(blk < G ? vA : vB) + (uint64_t)((int64_t)sl[blk] * (BB * ESZ));
-                const uint64_t neg = (uint64_t)(int64_t)(sl[blk] >> 31);
+                const T *base = blk < GP ? vA : (blk < G ? (DU == 2 ? vA2 : vA) : vB);
+                const uint64_t real = (uint64_t)base + (uint64_t)((int64_t)s_ * (BB * ESZ));
+                const uint64_t neg = (uint64_t)(int64_t)(s_ >> 31);
                 const char *g = reinterpret_cast<const char *>((real & ~neg) | ((uint64_t)zblk & neg)) + lane4;
                 dma_block<IPB, DW>(g, l, lane, std::make_integer_sequence<int, IPB>{});
             }
@@ -709,7 +724,7 @@ __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, co
     // ahead, up to D entries past the tile.  Entry counts are even, so for D = 2
     // both steps of an iteration are inside the tile.
     int asl[D][G];
-    int sbuf[D][NB];
+    int sbuf[D][NS];
     if (n > 0) {
         load_slots(0, sbuf[0]);
         load_slots(1, sbuf[1]);
@@ -742,7 +757,7 @@ __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, co
     for (int a = 0; a < G; ++a) {
         if (!cact[a]) continue;
         // TR: element (r, c) of D is element (c, r) of C's block
-        double *cp = vC + (int64_t)cs[a] * BB + (TR ? c * B : c);
+        double *cp = (DU == 2 && a >= GP ? vC2 : vC) + (int64_t)cs[a] * BB + (TR ? c * B : c);
         constexpr int RS = TR ? 1 : B;
         if (beta == 0.0) {
 #pragma unroll

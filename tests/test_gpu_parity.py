@@ -304,6 +304,69 @@ def test_product_variants_bitwise_equal(bsm, b):
             assert np.array_equal(got, ref), (variant, rows)
 
 
+@pytest.mark.parametrize("b", [4, 9])
+@pytest.mark.parametrize("cutoffs", [(14, 8, 8), (6, 8, 14), (8, 8, 8)])
+def test_product_pair_equals_two_products(bsm, b, cutoffs):
+    """bsm_multiply_truncate_pair (C = A B, C2 = A2 B sharing B's copies in one launch) gives
+    the bits of two bsm_multiply_truncate calls, which match the oracle; with a kernel variant
+    that has no paired tiles it runs as two launches; A2 or C2 off A's or C's pattern is refused."""
+    ra, rb, rc = cutoffs
+    s = SYSTEMS["si216_disp"]()
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in set(cutoffs)}
+    a = synth.random_blocks(op[ra].nnz, b, 150)
+    a2 = synth.random_blocks(op[ra].nnz, b, 151)
+    bb = synth.random_blocks(op[rb].nnz, b, 152)
+    c0 = synth.random_blocks(op[rc].nnz, b, 153)
+    c20 = synth.random_blocks(op[rc].nnz, b, 154)
+    got = {}
+    for variant in (-1, 1):
+        ctx = bsm.Context(0)
+        ctx.set_product_variant(variant)
+        say(f"pair product b={b} P{ra} x P{rb} -> P{rc}, variant {variant}")
+        gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in set(cutoffs)}
+        A, A2, B = gmat(bsm, gp[ra], a), gmat(bsm, gp[ra], a2), gmat(bsm, gp[rb], bb)
+        C, C2 = gmat(bsm, gp[rc], c0), gmat(bsm, gp[rc], c20)
+        bsm.multiply_truncate_pair(1.25, A, A2, B, -0.5, C, C2)
+        S1, S2 = gmat(bsm, gp[rc], c0), gmat(bsm, gp[rc], c20)
+        bsm.multiply_truncate(1.25, A, B, -0.5, S1)
+        bsm.multiply_truncate(1.25, A2, B, -0.5, S2)
+        assert np.array_equal(host(C), host(S1)) and np.array_equal(host(C2), host(S2)), variant
+        got[variant] = (host(C), host(C2))
+        if variant == -1:
+            other = gpat(bsm, ctx, s.positions, s.box, float(ra), b)   # same cutoff, another pattern
+            with pytest.raises(bsm.BSMError) as e:
+                bsm.multiply_truncate_pair(1.0, A, gmat(bsm, other, a2), B, 0.0, C, C2)
+            assert e.value.code == bsm.EPATTERN
+            with pytest.raises(bsm.BSMError) as e:
+                bsm.multiply_truncate_pair(1.0, A, A2, B, 0.0, C, C)
+            assert e.value.code == bsm.EINVAL
+        ctx.close()
+    for (x, x0, m) in ((got[-1][0], c0, a), (got[-1][1], c20, a2)):
+        Co = O.Matrix(op[rc], b, x0.copy())
+        O.multiply_truncate(1.25, O.Matrix(op[ra], b, m), O.Matrix(op[rb], b, bb), -0.5, Co)
+        assert rel_err(x, Co.blocks) < 1e-12
+
+
+def test_product_pair_at_4096_atoms(bsm):
+    """The paired launch on the 16 A x 16 A -> 16 A class of the 4096-atom, b = 9 system (the
+    pair LNV uses for W = X X and U = Y X): equal bits to two single products."""
+    pos, box, _ = synth.diamond_positions((8, 8, 8))
+    ctx = bsm.Context(0)
+    P = gpat(bsm, ctx, pos, box, 16.0, 9)
+    g = torch.Generator(device=ctx.device)
+    g.manual_seed(5)
+    mk = lambda: bsm.Matrix(P, torch.rand((P.nnzb, 9, 9), dtype=torch.float64, device=ctx.device, generator=g) - 0.5)
+    X, Y = mk(), mk()
+    W, U, W1, U1 = bsm.Matrix(P), bsm.Matrix(P), bsm.Matrix(P), bsm.Matrix(P)
+    say("pair product 4096 atoms b=9, 16 A")
+    bsm.multiply_truncate_pair(1.0, X, Y, X, 0.0, W, U)
+    bsm.multiply_truncate(1.0, X, X, 0.0, W1)
+    bsm.multiply_truncate(1.0, Y, X, 0.0, U1)
+    torch.cuda.synchronize()
+    assert torch.equal(W.blocks, W1.blocks) and torch.equal(U.blocks, U1.blocks)
+    ctx.close()
+
+
 @pytest.mark.parametrize("rows", [8, 4])
 @pytest.mark.parametrize("b", [4, 9])
 def test_transposed_plans_agree(bsm, b, rows):
