@@ -121,18 +121,23 @@ struct lnv_state_s {
         flops += plan->flops;
     }
     void mul(const Mat &A, const Mat &B, Mat &C) { mul(1.0, A.p, A.d(), B.p, B.d(), 0.0, C.p, C.d()); }
-    // C = A B and C2 = A2 B (A, A2 on one pattern): FP64 pairs share B's copies in one launch
-    // with the same results as two products
-    void mul_pair(const Mat &A, const Mat &A2, const Mat &B, Mat &C, Mat &C2)
+    // C = A B and C2 = A2 B (A, A2 on one pattern, C, C2 on one pattern): FP64 pairs share B's
+    // copies in one launch with the same results as two products
+    void mul_pair(const bsm_pattern_s *pa, const double *a, const double *a2, const bsm_pattern_s *pb,
+                  const double *b, const bsm_pattern_s *pc, double *c1, double *c2)
     {
-        Plan *pair = prec == BSM_F64 ? get_pair_plan(c, A.p, B.p, C.p) : nullptr;
+        Plan *pair = prec == BSM_F64 ? get_pair_plan(c, pa, pb, pc) : nullptr;
         if (!pair) {
-            mul(A, B, C);
-            mul(A2, B, C2);
+            mul(1.0, pa, a, pb, b, 0.0, pc, c1);
+            mul(1.0, pa, a2, pb, b, 0.0, pc, c2);
             return;
         }
-        launch_product_pair_f64(c, pair, 1.0, A.p, A.d(), A2.d(), B.p, B.d(), 0.0, C.p, C.d(), C2.d());
+        launch_product_pair_f64(c, pair, 1.0, pa, a, a2, pb, b, 0.0, pc, c1, c2);
         flops += 2.0 * pair->flops;
+    }
+    void mul_pair(const Mat &A, const Mat &A2, const Mat &B, Mat &C, Mat &C2)
+    {
+        mul_pair(A.p, A.d(), A2.d(), B.p, B.d(), C.p, C.d(), C2.d());
     }
     void precondition(const Mat &G, Mat &out)
     {
@@ -206,6 +211,20 @@ struct lnv_state_s {
     void gradients()
     {
         const int64_t nl = nelems(PL);
+        if (PH == PS) {
+            // H and S on one pattern: HX with SX and HW with SW as paired launches (B's copies
+            // shared); the same sums in the same order as below (PE is free until preconditioning)
+            mul_pair(PH, H, S, X.p, X.d(), PL, t1.d(), t2.d());      // HX, SX
+            add_transpose(c, PL, 6.0, t1.d(), 0.0, GE.d());        // 6 (HX + HX^T)
+            mul_pair(PH, H, S, W.p, W.d(), PL, t1.d(), PE.d());      // HW, SW
+            add_transpose(c, PL, -4.0, t1.d(), 1.0, GE.d());       // - 4 (HW + HW^T)
+            mul(1.0, PS, S, U.p, U.d(), 0.0, PL, t1.d());          // SU
+            axpby(c, nl, -4.0, t1.d(), 1.0, GE.d());               // - 4 SU
+            symmetrize(c, PL, GE.d());
+            axpbypcz(c, nl, 12.0, t2.d(), -12.0, PE.d(), 0.0, GN.d());
+            symmetrize(c, PL, GN.d());
+            return;
+        }
         mul(1.0, PH, H, X.p, X.d(), 0.0, PL, t1.d());          // HX
         add_transpose(c, PL, 6.0, t1.d(), 0.0, GE.d());        // 6 (HX + HX^T)
         mul(1.0, PH, H, W.p, W.d(), 0.0, PL, t1.d());          // HW
