@@ -873,7 +873,7 @@ def kernel_sources_sha() -> str:
 def kernel_name(st) -> str:
     b, g, v, p = st["b"], st["rows"], st["variant"], st.get("precision", 0)
     if st.get("products", 1) == 2:
-        return f"k_product_ring_pair<{b}, {2 * g}> (2 products sharing B on one {g}-row plan)"
+        return f"k_product_ring_pair<{b}, {2 * g}> (2 products sharing an operand, one {g}-row plan)"
     if p == 2 and b == 9 and g in (4, 8) and v in (3, 4):
         return f"k_product_mfma_bf16<{g}>"
     depth = 3 if v == 3 and g <= 4 else 2   # 8-row ring tiles run 1 entry ahead in both ring variants

@@ -247,6 +247,19 @@ int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const 
  * pattern; BSM_EINVAL when C or C2 aliases an operand or each other. */
 int bsm_multiply_truncate_pair(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *A2,
                                const bsm_matrix *B, double beta, const bsm_matrix *C, const bsm_matrix *C2);
+
+/* Two truncated products that share their left operand, in one launch:
+ * C <- alpha mask_{P_C}(A B) + beta C and C2 <- alpha mask_{P_C}(A B2) + beta C2,
+ * with B and B2 on one pattern and C and C2 on one pattern (Background).  For
+ * b = 4 and 9 with the default kernel the pair runs on a transposed plan
+ * (C = (B^T A^T)^T, all patterns being symmetric) as tiles of twice the rows of
+ * one 4-row plan, every copied block of A serving both products, each element
+ * equal bit for bit to what bsm_multiply_truncate gives; otherwise the two
+ * products run one after the other.  LNV evaluates X = L S with Y = L H, and
+ * X_D = D S with Y_D = D H, this way.  Asynchronous.  Errors: as
+ * bsm_multiply_truncate_pair, with B2 in the place of A2. */
+int bsm_multiply_truncate_pair_a(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *B,
+                                 const bsm_matrix *B2, double beta, const bsm_matrix *C, const bsm_matrix *C2);
 /* The same product with every element of A and B first rounded to `precision`:
  * BSM_F32 (round to nearest even) or BSM_BF16 (to FP32, then to 8 significant
  * bits, nearest even); products accumulated in FP32 by fused multiply-adds over

@@ -149,6 +149,9 @@ EXPORTS = {
     "bsm_multiply_truncate_pair": (c_int, [c_void_p, c_double, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
                                            ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix),
                                            ctypes.POINTER(_Matrix)]),
+    "bsm_multiply_truncate_pair_a": (c_int, [c_void_p, c_double, ctypes.POINTER(_Matrix), ctypes.POINTER(_Matrix),
+                                             ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix),
+                                             ctypes.POINTER(_Matrix)]),
     "bsm_product_flops": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double)]),
     "bsm_multiply_truncate_prec": (c_int, [c_void_p, c_int, c_double, ctypes.POINTER(_Matrix),
                                            ctypes.POINTER(_Matrix), c_double, ctypes.POINTER(_Matrix)]),
@@ -389,6 +392,14 @@ def multiply_truncate_pair(alpha: float, A: Matrix, A2: Matrix, B: Matrix, beta:
     pattern, C, C2 on one pattern)."""
     _check(_lib.bsm_multiply_truncate_pair(C.pattern.ctx.handle, float(alpha), A.c, A2.c, B.c, float(beta), C.c,
                                            C2.c))
+
+
+def multiply_truncate_pair_a(alpha: float, A: Matrix, B: Matrix, B2: Matrix, beta: float, C: Matrix,
+                             C2: Matrix) -> None:
+    """C <- alpha mask(A B) + beta C and C2 <- alpha mask(A B2) + beta C2 in one launch (B, B2 on one
+    pattern, C, C2 on one pattern)."""
+    _check(_lib.bsm_multiply_truncate_pair_a(C.pattern.ctx.handle, float(alpha), A.c, B.c, B2.c, float(beta), C.c,
+                                             C2.c))
 
 
 def multiply_truncate_prec(precision: int, alpha: float, A: Matrix, B: Matrix, beta: float, C: Matrix) -> None:

@@ -520,6 +520,40 @@ int bsm_multiply_truncate_pair(bsm_ctx ctx, double alpha, const bsm_matrix *A, c
     BSM_API_END
 }
 
+int bsm_multiply_truncate_pair_a(bsm_ctx ctx, double alpha, const bsm_matrix *A, const bsm_matrix *B,
+                                 const bsm_matrix *B2, double beta, const bsm_matrix *C, const bsm_matrix *C2)
+{
+    BSM_API_BEGIN
+    BSM_REQUIRE(ctx != nullptr, BSM_EINVAL, "ctx is NULL");
+    check_matrix(A, "A");
+    check_matrix(B, "B");
+    check_matrix(B2, "B2");
+    check_matrix(C, "C");
+    check_matrix(C2, "C2");
+    check_same_shape(A, B);
+    check_same_shape(A, C);
+    BSM_REQUIRE(B2->pattern == B->pattern, BSM_EPATTERN, "B2 must lie on B's pattern");
+    BSM_REQUIRE(C2->pattern == C->pattern, BSM_EPATTERN, "C2 must lie on C's pattern");
+    BSM_REQUIRE(!overlaps(C, A) && !overlaps(C, B) && !overlaps(C, B2) && !overlaps(C2, A) &&
+                    !overlaps(C2, B) && !overlaps(C2, B2) && !overlaps(C, C2),
+                BSM_EINVAL, "C or C2 overlaps an operand or each other");
+    Context *c = &ctx->c;
+    Plan *pair = get_pair_plan_a(c, A->pattern, B->pattern, C->pattern);
+    if (pair) {
+        launch_product_pair_a_f64(c, pair, alpha, A->pattern, (const double *)A->blocks, B->pattern,
+                                  (const double *)B->blocks, (const double *)B2->blocks, beta, C->pattern,
+                                  (double *)C->blocks, (double *)C2->blocks);
+    } else {
+        Plan *plan = get_plan(c, A->pattern, B->pattern, C->pattern);
+        launch_product_f64(c, plan, alpha, A->pattern, (const double *)A->blocks, B->pattern,
+                           (const double *)B->blocks, beta, C->pattern, (double *)C->blocks);
+        launch_product_f64(c, plan, alpha, A->pattern, (const double *)A->blocks, B->pattern,
+                           (const double *)B2->blocks, beta, C->pattern, (double *)C2->blocks);
+    }
+    return BSM_OK;
+    BSM_API_END
+}
+
 int bsm_multiply_truncate_prec(bsm_ctx ctx, int precision, double alpha, const bsm_matrix *A,
                                const bsm_matrix *B, double beta, const bsm_matrix *C)
 {

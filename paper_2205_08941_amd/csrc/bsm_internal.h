@@ -188,6 +188,14 @@ Plan *get_pair_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *
 void launch_product_pair_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
                              const double *A, const double *A2, const bsm_pattern_s *PB, const double *B,
                              double beta, const bsm_pattern_s *PC, double *C, double *C2);
+// The same for two products sharing their left operand (C = alpha A B + beta C and C2 = alpha A B2 +
+// beta C2, B and B2 on PB), on a transposed 4-row plan (C = (B^T A^T)^T); nullptr as above.
+Plan *get_pair_plan_a(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC);
+void launch_product_pair_a_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
+                               const double *A, const bsm_pattern_s *PB, const double *B, const double *B2,
+                               double beta, const bsm_pattern_s *PC, double *C, double *C2);
+// A transposed ring plan (variant 4) of G rows, cached apart from the plans get_plan_kind picks.
+Plan *get_transposed_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C, int G);
 void build_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC,
                 Plan *plan, int G, int waves, int transposed = 0);
 // prec BSM_F64: the FP64 product; BSM_F32 / BSM_BF16: operands rounded to that

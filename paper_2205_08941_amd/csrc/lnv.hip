@@ -139,6 +139,18 @@ struct lnv_state_s {
     {
         mul_pair(A.p, A.d(), A2.d(), B.p, B.d(), C.p, C.d(), C2.d());
     }
+    // C = A S and C2 = A H (the left operand shared): one launch when H and S lie on one pattern
+    void mul_pair_sh(const bsm_pattern_s *pa, const double *a, const bsm_pattern_s *pc, double *c1, double *c2)
+    {
+        Plan *pair = prec == BSM_F64 && PH == PS ? get_pair_plan_a(c, pa, PS, pc) : nullptr;
+        if (!pair) {
+            mul(1.0, pa, a, PS, S, 0.0, pc, c1);
+            mul(1.0, pa, a, PH, H, 0.0, pc, c2);
+            return;
+        }
+        launch_product_pair_a_f64(c, pair, 1.0, pa, a, PS, S, H, 0.0, pc, c1, c2);
+        flops += 2.0 * pair->flops;
+    }
     void precondition(const Mat &G, Mat &out)
     {
         mul(1.0, PZ, Z, G.p, G.d(), 0.0, ZG.p, ZG.d());
@@ -196,8 +208,7 @@ struct lnv_state_s {
     // E = 2 Tr KH and N = 2 Tr KS of the current L (X = LS, Y = LH, W = XX on P_X)
     void energy(double &E, double &N)
     {
-        mul(1.0, PL, L, PS, S, 0.0, X.p, X.d());
-        mul(1.0, PL, L, PH, H, 0.0, Y.p, Y.d());
+        mul_pair_sh(PL, L, X.p, X.d(), Y.d());                   // X = L S, Y = L H
         mul(X, X, W);
         double tr[4];   // Tr XY, Tr WY, Tr XX, Tr WX
         const double *a[2] = {X.d(), W.d()}, *b[2] = {Y.d(), X.d()};
@@ -386,8 +397,7 @@ int lnv_state_s::step(lnv_result *res)
         Mat &X = st->X, &Y = st->Y, &W = st->W, &U = st->U, &XD = st->XD, &YD = st->YD, &Q = st->Q, &W1 = st->W1;
 
         // ---- evaluate: X = LS, Y = LH, W = XX, U = YX; E, N from traces
-        st->mul(1.0, PL, st->L, st->PS, st->S, 0.0, X.p, X.d());
-        st->mul(1.0, PL, st->L, st->PH, st->H, 0.0, Y.p, Y.d());
+        st->mul_pair_sh(PL, st->L, X.p, X.d(), Y.d());               // X = L S, Y = L H
         st->mul_pair(X, Y, X, W, U);                                 // W = X X, U = Y X
         double tr0[4];
         {
@@ -443,8 +453,7 @@ int lnv_state_s::step(lnv_result *res)
         }
 
         // ---- exact line search along L + a D
-        st->mul(1.0, PL, D.d(), st->PS, st->S, 0.0, XD.p, XD.d());   // X_D = D S
-        st->mul(1.0, PL, D.d(), st->PH, st->H, 0.0, YD.p, YD.d());   // Y_D = D H
+        st->mul_pair_sh(PL, D.d(), XD.p, XD.d(), YD.d());            // X_D = D S, Y_D = D H
         st->mul(XD, XD, Q);                                          // Q = X_D X_D
         axpbypcz(c, nx, 1.0, X.d(), 1.0, XD.d(), 0.0, U.d());        // X1 = X + X_D (U is free now)
         st->mul(U, U, W1);                                           // W1 = X1 X1
@@ -564,8 +573,7 @@ extern "C" int lnv_forces(lnv_state *st, const bsm_matrix *dS, const bsm_matrix 
         const int64_t ns = nelems(PS);
         Mat &X = st->X, &Y = st->Y, &W = st->W, &U = st->U;
         // chemical potential at the current L (canonical definition), as a step computes it
-        st->mul(1.0, PL, st->L, PS, st->S, 0.0, X.p, X.d());
-        st->mul(1.0, PL, st->L, PH, st->H, 0.0, Y.p, Y.d());
+        st->mul_pair_sh(PL, st->L, X.p, X.d(), Y.d());               // X = L S, Y = L H
         st->mul_pair(X, Y, X, W, U);                                 // W = X X, U = Y X
         st->gradients();
         st->precondition(st->GE, st->PE);

@@ -103,8 +103,9 @@ __global__ __launch_bounds__(64 * W) void k_product_ring(
 }
 
 // Two products sharing B and the patterns (C = A B, C2 = A2 B) on one plan of G / 2
-// rows: one wave tile of G rows per one-wave workgroup, B's copies serving both.
-template <int B, int G, bool BUF>
+// rows: one wave tile of G rows per one-wave workgroup, B's copies serving both
+// (TR = 1: a transposed plan, the launch passing the shared left operand as B).
+template <int B, int G, bool BUF, int TR = 0>
 __global__ __launch_bounds__(64) void k_product_ring_pair(
     int64_t ntiles, int64_t nwg_padded, const int *__restrict__ order, const int *__restrict__ hdr,
     const int64_t *__restrict__ ebeg, const int *__restrict__ ent, const double *__restrict__ vA,
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(64) void k_product_ring_pair(
     __shared__ __attribute__((aligned(16))) char ring[2 * RingEntry<B, G, double>::kBytes];
     const int64_t t = logical_workgroup(nwg_padded);
     if (t >= ntiles) return;
-    tile_ring<B, G, 2, double, BUF, 1, 0, 2>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta,
+    tile_ring<B, G, 2, double, BUF, 1, TR, 2>(order[t], hdr, ebeg, ent, vA, vB, zblk, vC, alpha, beta,
                                              (lds_char_t *)ring, a_bytes, b_bytes, vA2, vC2, a2_bytes);
 }
 
@@ -826,19 +827,19 @@ Plan *get_pair_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *
 }
 
 namespace {
-template <int B>
+template <int B, int TR>
 void launch_pair(hipStream_t st, const Plan *plan, const double *A, const double *A2, const double *Bm, double *C,
                  double *C2, double alpha, double beta, const double *zblk, int64_t a_bytes, int64_t b_bytes)
 {
     const int64_t nwg_padded = ((plan->ntiles + kXcd - 1) / kXcd) * kXcd;
     const bool buf = a_bytes <= (int64_t)kBufMaxBytes && b_bytes <= (int64_t)kBufMaxBytes;
     if (buf)
-        k_product_ring_pair<B, 8, true><<<(unsigned)nwg_padded, 64, 0, st>>>(
+        k_product_ring_pair<B, 8, true, TR><<<(unsigned)nwg_padded, 64, 0, st>>>(
             plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
             plan->ent.as<int>(), A, A2, Bm, zblk, C, C2, alpha, beta, (unsigned)a_bytes, (unsigned)a_bytes,
             (unsigned)b_bytes);
     else
-        k_product_ring_pair<B, 8, false><<<(unsigned)nwg_padded, 64, 0, st>>>(
+        k_product_ring_pair<B, 8, false, TR><<<(unsigned)nwg_padded, 64, 0, st>>>(
             plan->ntiles, nwg_padded, plan->order.as<int>(), plan->hdr.as<int>(), plan->ebeg.as<int64_t>(),
             plan->ent.as<int>(), A, A2, Bm, zblk, C, C2, alpha, beta, 0u, 0u, 0u);
 }
@@ -860,9 +861,52 @@ void launch_product_pair_f64(Context *ctx, const Plan *plan, double alpha, const
     }
     const int64_t ab = 8 * nelems(PA), bb = 8 * nelems(PB);
     if (PC->b == 9)
-        launch_pair<9>(st, plan, A, A2, Bm, C, C2, alpha, beta, ctx->zero_block.as<double>(), ab, bb);
+        launch_pair<9, 0>(st, plan, A, A2, Bm, C, C2, alpha, beta, ctx->zero_block.as<double>(), ab, bb);
     else
-        launch_pair<4>(st, plan, A, A2, Bm, C, C2, alpha, beta, ctx->zero_block.as<double>(), ab, bb);
+        launch_pair<4, 0>(st, plan, A, A2, Bm, C, C2, alpha, beta, ctx->zero_block.as<double>(), ab, bb);
+    BSM_HIP_TRY(hipGetLastError());
+    if (ctx->profiling) {
+        BSM_HIP_TRY(hipEventRecord(rec.stop, st));
+        ctx->prof.push_back(rec);
+    }
+}
+
+Plan *get_pair_plan_a(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC)
+{
+    const int b = PC->b;
+    if (b != 4 && b != 9) return nullptr;
+    if (ctx->product_variant >= 0 && ctx->product_variant != 4) return nullptr;
+    // transposed 4-row ring plan: the tiles' rows walk B and B2, the shared A is the copied operand
+    auto it = ctx->plans.find(std::make_tuple(PA->id, PB->id, PC->id, 4, 4, 2));
+    if (it != ctx->plans.end()) return it->second.get();
+    const Plan *one = get_plan(ctx, PA, PB, PC);
+    const double est = 1.3 * (double)(one->ent.bytes + one->hdr.bytes + one->order.bytes + one->ebeg.bytes);
+    size_t free_b = 0, total_b = 0;
+    BSM_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    if ((double)free_b < 2.0 * est + 8.0 * (1u << 30)) return nullptr;
+    return get_transposed_plan(ctx, PA, PB, PC, 4);
+}
+
+void launch_product_pair_a_f64(Context *ctx, const Plan *plan, double alpha, const bsm_pattern_s *PA,
+                               const double *A, const bsm_pattern_s *PB, const double *Bm, const double *B2,
+                               double beta, const bsm_pattern_s *PC, double *C, double *C2)
+{
+    BSM_REQUIRE(plan->variant == 4 && plan->G == 4 && plan->transposed && (PC->b == 4 || PC->b == 9),
+                BSM_EINVAL, "a paired launch sharing A takes a transposed 4-row ring plan, b = 4 or 9");
+    if (plan->ntiles == 0) return;
+    hipStream_t st = ctx->stream;
+    Context::ProfRec rec{plan, nullptr, nullptr, BSM_F64, 2};
+    if (ctx->profiling) {
+        rec.start = ctx->take_event();
+        rec.stop = ctx->take_event();
+        BSM_HIP_TRY(hipEventRecord(rec.start, st));
+    }
+    // the kernel's row operand is B (and B2), its column operand the shared A
+    const int64_t ab = 8 * nelems(PB), bb = 8 * nelems(PA);
+    if (PC->b == 9)
+        launch_pair<9, 1>(st, plan, Bm, B2, A, C, C2, alpha, beta, ctx->zero_block.as<double>(), ab, bb);
+    else
+        launch_pair<4, 1>(st, plan, Bm, B2, A, C, C2, alpha, beta, ctx->zero_block.as<double>(), ab, bb);
     BSM_HIP_TRY(hipGetLastError());
     if (ctx->profiling) {
         BSM_HIP_TRY(hipEventRecord(rec.stop, st));
@@ -950,6 +994,34 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
 // measurement.
 static double plan_cost(const Plan *p) { return (double)p->rowwork + 4.5 * (double)p->nentries; }
 
+static std::unique_ptr<Plan> new_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B,
+                                      const bsm_pattern_s *C, int variant, int G, int transposed)
+{
+    std::unique_ptr<Plan> plan(new Plan());
+    plan->ids[0] = A->id;
+    plan->ids[1] = B->id;
+    plan->ids[2] = C->id;
+    plan->cutoffs[0] = A->cutoff;
+    plan->cutoffs[1] = B->cutoff;
+    plan->cutoffs[2] = C->cutoff;
+    plan->natoms = C->natoms;
+    plan->b = C->b;
+    build_plan(ctx, A, B, C, plan.get(), G, variant == 5 ? 2 : 1, transposed);
+    plan->variant = variant;
+    return plan;
+}
+
+Plan *get_transposed_plan(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C, int G)
+{
+    auto key = std::make_tuple(A->id, B->id, C->id, 4, G, 2);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) return it->second.get();
+    std::unique_ptr<Plan> plan = new_plan(ctx, A, B, C, 4, G, 1);
+    Plan *raw = plan.get();
+    ctx->plans[key] = std::move(plan);
+    return raw;
+}
+
 Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B, const bsm_pattern_s *C,
                     int variant, int G, bool allow_transposed)
 {
@@ -961,20 +1033,7 @@ Plan *get_plan_kind(Context *ctx, const bsm_pattern_s *A, const bsm_pattern_s *B
     auto key = std::make_tuple(A->id, B->id, C->id, variant, G, try_t ? 1 : 0);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) return it->second.get();
-    auto make = [&](int transposed) {
-        std::unique_ptr<Plan> plan(new Plan());
-        plan->ids[0] = A->id;
-        plan->ids[1] = B->id;
-        plan->ids[2] = C->id;
-        plan->cutoffs[0] = A->cutoff;
-        plan->cutoffs[1] = B->cutoff;
-        plan->cutoffs[2] = C->cutoff;
-        plan->natoms = C->natoms;
-        plan->b = C->b;
-        build_plan(ctx, A, B, C, plan.get(), G, variant == 5 ? 2 : 1, transposed);
-        plan->variant = variant;
-        return plan;
-    };
+    auto make = [&](int transposed) { return new_plan(ctx, A, B, C, variant, G, transposed); };
     std::unique_ptr<Plan> plan = ctx->transposed_plans == 2 && try_t ? make(1) : make(0);
     if (try_t && ctx->transposed_plans == 1) {
         std::unique_ptr<Plan> alt = make(1);

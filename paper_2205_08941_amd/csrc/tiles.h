@@ -585,8 +585,10 @@ constexpr unsigned kBufMaxBytes = 0xfffff000u;
 // same order as the direct product.
 // DU = 2: two products that share B and the patterns, C = A B and C2 = A2 B, on
 // one plan of G / 2 rows: the tile's first G / 2 rows multiply A's blocks, the
-// other G / 2 the same slots of A2, and every B block copied serves both.  Each
-// product's elements sum the same terms in the same order as its own launch.
+// other G / 2 the same slots of A2, and every B block copied serves both (with
+// TR = 1 on a transposed plan: C = (B^T A^T)^T and C2 = (B^T A2^T)^T, i.e. two
+// products sharing their left operand).  Each product's elements sum the same
+// terms in the same order as its own launch.
 template <int B, int G, int D, class T = double, bool BUF = false, int W = 1, int TR = 0, int DU = 1>
 __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, const int *__restrict__ hdr, const int64_t *__restrict__ ebeg,
                                  const int *__restrict__ ent, const T *__restrict__ vA, const T *__restrict__ vB,
@@ -598,7 +600,7 @@ __device__ __attribute__((always_inline)) inline void tile_ring(int64_t tile, co
     using RE = RingEntry<B, G, T>;
     static_assert(W == 1 || W == 2, "one or two waves per tile");
     static_assert(TR == 0 || W == 1, "transposed products use one-wave tiles");
-    static_assert(DU == 1 || (DU == 2 && W == 1 && TR == 0 && G % 2 == 0), "paired products: one-wave direct tiles");
+    static_assert(DU == 1 || (DU == 2 && W == 1 && G % 2 == 0), "paired products: one-wave tiles");
     constexpr int ESZ = (int)sizeof(T);
     constexpr int JT = 64 / B;
     constexpr int BB = B * B;

@@ -347,6 +347,46 @@ def test_product_pair_equals_two_products(bsm, b, cutoffs):
         assert rel_err(x, Co.blocks) < 1e-12
 
 
+@pytest.mark.parametrize("b", [4, 9])
+@pytest.mark.parametrize("cutoffs", [(8, 6, 14), (14, 8, 8), (8, 8, 8)])
+def test_product_pair_a_equals_two_products(bsm, b, cutoffs):
+    """bsm_multiply_truncate_pair_a (C = A B, C2 = A B2 sharing A's copies, on a transposed plan)
+    gives the bits of two bsm_multiply_truncate calls, which match the oracle; with a kernel
+    variant that has no paired tiles it runs as two launches; B2 off B's pattern is refused."""
+    ra, rb, rc = cutoffs
+    s = SYSTEMS["si216_disp"]()
+    op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in set(cutoffs)}
+    a = synth.random_blocks(op[ra].nnz, b, 160)
+    bb = synth.random_blocks(op[rb].nnz, b, 161)
+    bb2 = synth.random_blocks(op[rb].nnz, b, 162)
+    c0 = synth.random_blocks(op[rc].nnz, b, 163)
+    c20 = synth.random_blocks(op[rc].nnz, b, 164)
+    got = None
+    for variant in (-1, 1):
+        ctx = bsm.Context(0)
+        ctx.set_product_variant(variant)
+        say(f"pair_a product b={b} P{ra} x P{rb} -> P{rc}, variant {variant}")
+        gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in set(cutoffs)}
+        A, B, B2 = gmat(bsm, gp[ra], a), gmat(bsm, gp[rb], bb), gmat(bsm, gp[rb], bb2)
+        C, C2 = gmat(bsm, gp[rc], c0), gmat(bsm, gp[rc], c20)
+        bsm.multiply_truncate_pair_a(1.25, A, B, B2, -0.5, C, C2)
+        S1, S2 = gmat(bsm, gp[rc], c0), gmat(bsm, gp[rc], c20)
+        bsm.multiply_truncate(1.25, A, B, -0.5, S1)
+        bsm.multiply_truncate(1.25, A, B2, -0.5, S2)
+        assert np.array_equal(host(C), host(S1)) and np.array_equal(host(C2), host(S2)), variant
+        if variant == -1:
+            got = (host(C), host(C2))
+            other = gpat(bsm, ctx, s.positions, s.box, float(rb), b)
+            with pytest.raises(bsm.BSMError) as e:
+                bsm.multiply_truncate_pair_a(1.0, A, B, gmat(bsm, other, bb2), 0.0, C, C2)
+            assert e.value.code == bsm.EPATTERN
+        ctx.close()
+    for (x, x0, m) in ((got[0], c0, bb), (got[1], c20, bb2)):
+        Co = O.Matrix(op[rc], b, x0.copy())
+        O.multiply_truncate(1.25, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, m), -0.5, Co)
+        assert rel_err(x, Co.blocks) < 1e-12
+
+
 def test_product_pair_at_4096_atoms(bsm):
     """The paired launch on the 16 A x 16 A -> 16 A class of the 4096-atom, b = 9 system (the
     pair LNV uses for W = X X and U = Y X): equal bits to two single products."""
