@@ -806,6 +806,16 @@ void launch_product_f64(Context *ctx, const Plan *plan, double alpha, const bsm_
     }
 }
 
+// A paired launch's 4-row plan, estimated from the class's default plan (about 1.3 times its
+// size), fits when free device memory holds twice the estimate and a quarter of the device more.
+static bool pair_plan_fits(Context *ctx, const Plan *one)
+{
+    const double est = 1.3 * (double)(one->ent.bytes + one->hdr.bytes + one->order.bytes + one->ebeg.bytes);
+    size_t free_b = 0, total_b = 0;
+    BSM_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    return (double)free_b >= 2.0 * est + std::max(8.0 * (1u << 30), 0.25 * (double)total_b);
+}
+
 Plan *get_pair_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *PB, const bsm_pattern_s *PC)
 {
     const int b = PC->b;
@@ -816,13 +826,9 @@ Plan *get_pair_plan(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s *
     if (it != ctx->plans.end()) return it->second.get();
     // The 4-row plan is a second plan beside the default one (about 1.3 times its size, 4.9 GB
     // for the 16 A class at 4096 atoms, eight times that at 32768): built only while free
-    // device memory holds twice that and 8 GB more, else the pair runs as two launches (same
-    // results either way)
-    const Plan *one = get_plan(ctx, PA, PB, PC);
-    const double est = 1.3 * (double)(one->ent.bytes + one->hdr.bytes + one->order.bytes + one->ebeg.bytes);
-    size_t free_b = 0, total_b = 0;
-    BSM_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    if ((double)free_b < 2.0 * est + 8.0 * (1u << 30)) return nullptr;
+    // device memory holds twice that and a quarter of the device besides (room for what the
+    // caller allocates next), else the pair runs as two launches (same results either way)
+    if (!pair_plan_fits(ctx, get_plan(ctx, PA, PB, PC))) return nullptr;
     return get_plan_kind(ctx, PA, PB, PC, 4, 4);
 }
 
@@ -879,11 +885,7 @@ Plan *get_pair_plan_a(Context *ctx, const bsm_pattern_s *PA, const bsm_pattern_s
     // transposed 4-row ring plan: the tiles' rows walk B and B2, the shared A is the copied operand
     auto it = ctx->plans.find(std::make_tuple(PA->id, PB->id, PC->id, 4, 4, 2));
     if (it != ctx->plans.end()) return it->second.get();
-    const Plan *one = get_plan(ctx, PA, PB, PC);
-    const double est = 1.3 * (double)(one->ent.bytes + one->hdr.bytes + one->order.bytes + one->ebeg.bytes);
-    size_t free_b = 0, total_b = 0;
-    BSM_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    if ((double)free_b < 2.0 * est + 8.0 * (1u << 30)) return nullptr;
+    if (!pair_plan_fits(ctx, get_plan(ctx, PA, PB, PC))) return nullptr;
     return get_transposed_plan(ctx, PA, PB, PC, 4);
 }
 
