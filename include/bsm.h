@@ -252,7 +252,8 @@ int bsm_multiply_truncate_pair(bsm_ctx ctx, double alpha, const bsm_matrix *A, c
  * C <- alpha mask_{P_C}(A B) + beta C and C2 <- alpha mask_{P_C}(A B2) + beta C2,
  * with B and B2 on one pattern and C and C2 on one pattern (Background).  For
  * b = 4 and 9 with the default kernel the pair runs on a transposed plan
- * (C = (B^T A^T)^T, all patterns being symmetric) as tiles of twice the rows of
+ * (C = (B^T A^T)^T, all patterns being symmetric; whatever
+ * bsm_ctx_set_transposed_plans sets for single products) as tiles of twice the rows of
  * one 4-row plan, every copied block of A serving both products, each element
  * equal bit for bit to what bsm_multiply_truncate gives; otherwise the two
  * products run one after the other.  LNV evaluates X = L S with Y = L H, and
