@@ -141,3 +141,35 @@ def test_solve_matches_stored_oracle(bsm, case):
         e = lnv.idempotency_error()
         say(f"[{case}] idempotency error {e:.6e} (oracle {gl['idempotency_error']:.6e})")
         assert abs(e - gl["idempotency_error"]) <= 1e-8 * gl["idempotency_error"]
+
+
+def test_paired_launches_leave_the_solve_unchanged(bsm):
+    """The solve with paired launches (default kernel) and without them (variant 3: the same ring
+    tiles, single launches only) gives the same bits: Hotelling residuals, every LNV E, N and alpha,
+    and the final L (512 displaced atoms, truncated L, S^-1 and S patterns, 8 LNV steps)."""
+    s = system("si512_b9_disp")
+    cut = s.cutoffs
+    out = []
+    for variant in (-1, 3):
+        ctx = bsm.Context(0)
+        ctx.set_product_variant(variant)
+        say(f"paired launches: variant {variant}")
+        pos = torch.tensor(s.positions, dtype=torch.float64, device=ctx.device)
+        PS = bsm.Pattern(ctx, pos, s.box, cut["S"], s.b)
+        PZ = bsm.Pattern(ctx, pos, s.box, cut["Z"], s.b)
+        PL = bsm.Pattern(ctx, pos, s.box, cut["L"], s.b)
+        S, H, Z, L = bsm.Matrix(PS), bsm.Matrix(PS), bsm.Matrix(PZ), bsm.Matrix(PL)
+        bsm.fill_blocks(S, s.S.rows, s.S.cols, s.S.blocks)
+        bsm.fill_blocks(H, s.H.rows, s.H.cols, s.H.blocks)
+        ctx.set_profiling(True)
+        hr = bsm.hotelling_inverse(S, Z, max_iter=100, tol=1e-12)
+        lnv = bsm.LNV(S, H, Z, L, s.n_electrons, init_from_z=True)
+        steps = [lnv.step() for _ in range(8)]
+        out.append((list(hr.residuals), [(r.E, r.N, r.alpha) for r in steps], L.blocks.cpu().numpy()))
+        paired = sum(st["launches"] for st in ctx.product_stats() if st["products"] == 2)
+        say(f"   paired launches: {paired}")
+        assert (paired > 0) == (variant == -1)
+        ctx.close()
+    assert out[0][0] == out[1][0]
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
