@@ -387,6 +387,35 @@ def test_product_pair_a_equals_two_products(bsm, b, cutoffs):
         assert rel_err(x, Co.blocks) < 1e-12
 
 
+@pytest.mark.parametrize("b", [4, 9])
+def test_product_pairs_degenerate(bsm, b):
+    """Pairs on one atom (one tile, one entry padded to two) and on diagonal-only operands into a
+    wide output pattern (most tiles have no entries and only apply beta): equal bits to single
+    products, for both the shared-right and the shared-left pair."""
+    ctx = bsm.Context(0)
+    one = np.array([[1.0, 2.0, 3.0]])
+    s = SYSTEMS["si216_disp"]()
+    cases = [(gpat(bsm, ctx, one, (5.0, 5.0, 5.0), 2.0, b),) * 3]
+    gd, g6 = gpat(bsm, ctx, s.positions, s.box, 1.0, b), gpat(bsm, ctx, s.positions, s.box, 6.0, b)
+    cases.append((gd, gd, g6))
+    for n, (pa, pb, pc) in enumerate(cases):
+        say(f"degenerate pairs b={b} case {n}")
+        rnd = lambda P, seed: gmat(bsm, P, synth.random_blocks(P.nnzb, b, seed))
+        A, A2, B, B2 = rnd(pa, 10 + n), rnd(pa, 20 + n), rnd(pb, 30 + n), rnd(pb, 40 + n)
+        c0, c20 = synth.random_blocks(pc.nnzb, b, 50 + n), synth.random_blocks(pc.nnzb, b, 60 + n)
+        C, C2, S1, S2 = gmat(bsm, pc, c0), gmat(bsm, pc, c20), gmat(bsm, pc, c0), gmat(bsm, pc, c20)
+        bsm.multiply_truncate_pair(1.5, A, A2, B, -0.25, C, C2)
+        bsm.multiply_truncate(1.5, A, B, -0.25, S1)
+        bsm.multiply_truncate(1.5, A2, B, -0.25, S2)
+        assert np.array_equal(host(C), host(S1)) and np.array_equal(host(C2), host(S2))
+        C, C2, S1, S2 = gmat(bsm, pc, c0), gmat(bsm, pc, c20), gmat(bsm, pc, c0), gmat(bsm, pc, c20)
+        bsm.multiply_truncate_pair_a(1.5, A, B, B2, -0.25, C, C2)
+        bsm.multiply_truncate(1.5, A, B, -0.25, S1)
+        bsm.multiply_truncate(1.5, A, B2, -0.25, S2)
+        assert np.array_equal(host(C), host(S1)) and np.array_equal(host(C2), host(S2))
+    ctx.close()
+
+
 def test_product_pair_at_4096_atoms(bsm):
     """The paired launch on the 16 A x 16 A -> 16 A class of the 4096-atom, b = 9 system (the
     pair LNV uses for W = X X and U = Y X): equal bits to two single products."""
