@@ -116,7 +116,7 @@ typedef struct {
     double ms;           /* summed event time, milliseconds */
     int variant, rows;   /* kernel variant (bsm_ctx_set_product_variant) and rows per tile */
     int precision;       /* BSM_F64, BSM_F32 or BSM_BF16 */
-    int products;        /* products per launch: 1, or 2 for bsm_multiply_truncate_pair */
+    int products;        /* products per launch: 1, or 2 for the paired launches */
 } bsm_product_stat;
 
 /* Rows of C per wavefront tile in product plans built from now on: 2, 4 or 8
@@ -238,8 +238,10 @@ int bsm_multiply_truncate(bsm_ctx ctx, double alpha, const bsm_matrix *A, const 
 /* Two truncated products that share their right operand, in one launch:
  * C <- alpha mask_{P_C}(A B) + beta C and C2 <- alpha mask_{P_C}(A2 B) + beta C2,
  * with A and A2 on one pattern and C and C2 on one pattern (the same products as
- * bsm_multiply_truncate, Background).  For b = 4 and 9 with the default kernel
- * the pair runs as tiles of twice the rows of one 4-row plan: every copied block
+ * bsm_multiply_truncate, Background).  For b = 4 and 9 with the default kernel,
+ * while the pair's 4-row plan fits (free device memory of twice its estimated
+ * size and a quarter of the device; it is cached beside the class's default
+ * plan), the pair runs as tiles of twice the rows of that plan: every copied block
  * of B serves both products, and each element of C and C2 equals, bit for bit,
  * what bsm_multiply_truncate gives; otherwise the two products run one after the
  * other.  LNV evaluates W = X X and U = Y X this way.  Asynchronous.  Errors: as
@@ -251,8 +253,8 @@ int bsm_multiply_truncate_pair(bsm_ctx ctx, double alpha, const bsm_matrix *A, c
 /* Two truncated products that share their left operand, in one launch:
  * C <- alpha mask_{P_C}(A B) + beta C and C2 <- alpha mask_{P_C}(A B2) + beta C2,
  * with B and B2 on one pattern and C and C2 on one pattern (Background).  For
- * b = 4 and 9 with the default kernel the pair runs on a transposed plan
- * (C = (B^T A^T)^T, all patterns being symmetric; whatever
+ * b = 4 and 9 with the default kernel, while its plan fits as above, the pair
+ * runs on a transposed plan (C = (B^T A^T)^T, all patterns being symmetric; whatever
  * bsm_ctx_set_transposed_plans sets for single products) as tiles of twice the rows of
  * one 4-row plan, every copied block of A serving both products, each element
  * equal bit for bit to what bsm_multiply_truncate gives; otherwise the two
