@@ -268,9 +268,9 @@ int bsm_multiply_truncate_pair_a(bsm_ctx ctx, double alpha, const bsm_matrix *A,
  * bits, nearest even); products accumulated in FP32 by fused multiply-adds over
  * k ascending, then the block's inner index ascending; the FP32 sum is widened
  * exactly to FP64 and C <- alpha sum + beta C in FP64.  Exception: BSM_BF16 with
- * b = 9, kernel variant 3 or 4 and 4 or 8 rows per tile runs on the matrix
- * cores (products exact in FP32, summed in FP32 in the matrix core's order), so its sums differ from the FMA
- * chain by FP32 rounding.  BSM_F64 is bsm_multiply_truncate.  A and B stay FP64
+ * b = 9, A and B on one pattern, kernel variant 3 or 4 and 4 or 8 rows per tile
+ * runs on the matrix cores (products exact in FP32, summed in FP32 in the matrix
+ * core's order), so its sums differ from the FMA chain by FP32 rounding.  BSM_F64 is bsm_multiply_truncate.  A and B stay FP64
  * in memory; their rounded (or packed) copies live in context scratch.  Used for
  * the low-precision stages of an LNV solve with FP64 traces and refinement (an
  * extension built on the method, not in the paper). */

@@ -927,12 +927,15 @@ void launch_product_mixed(Context *ctx, const Plan *plan, int prec, double alpha
     BSM_REQUIRE(prec == BSM_F32 || prec == BSM_BF16, BSM_EINVAL, "precision must be F64, F32 or BF16");
     if (plan->G > 8) plan = get_plan_kind(ctx, PA, PB, PC, 0, default_rows_per_wave(PC->b));   // wave tiles
     if (plan->variant == 6) plan = get_plan_kind(ctx, PA, PB, PC, 4, plan->G);   // reduced precision: the ring
-    if (prec == BSM_BF16 && PC->b == 9 && (plan->variant == 5 || plan->transposed))
+    // BF16 on the matrix cores for products of two matrices on one pattern (the wide 16 A class,
+    // where the dense MFMA tiles pay); the narrower classes run faster on the FP32 VALU ring with
+    // BF16-rounded operands, on their own (possibly transposed) plans
+    const bool mfma = prec == BSM_BF16 && PC->b == 9 && PA == PB;
+    if (mfma && (plan->variant == 5 || plan->transposed))
         plan = get_plan_kind(ctx, PA, PB, PC, 4, plan->G);   // the matrix cores take direct one-wave tiles
     if (plan->ntiles == 0) return;
     hipStream_t st = ctx->stream;
-    if (prec == BSM_BF16 && PC->b == 9 && (plan->G == 4 || plan->G == 8) &&
-        (plan->variant == 3 || plan->variant == 4)) {
+    if (mfma && (plan->G == 4 || plan->G == 8) && (plan->variant == 3 || plan->variant == 4)) {
         // matrix cores: operands packed to BF16 (B transposed), FP32 accumulation
         unsigned short *pa = reinterpret_cast<unsigned short *>(ctx->scratch_f32(0, PA->nnzb * (kPackedBlock / 2)));
         unsigned short *pb = reinterpret_cast<unsigned short *>(ctx->scratch_f32(1, PB->nnzb * (kPackedBlock / 2)));

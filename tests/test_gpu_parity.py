@@ -759,7 +759,8 @@ def test_mixed_product_parity(bsm, prec, b, variant, rows):
     FP32 products, summed in the matrix core's order, so the sums differ from the
     oracle's FMA chain by FP32 rounding only: checked against the oracle at 2e-6 of
     the result scale (a few hundred terms per element, FP32 unit roundoff 6e-8).
-    4- and 8-row tiles both run BF16 on the matrix cores."""
+    4- and 8-row tiles both run BF16 on the matrix cores when A and B share a pattern;
+    products of two patterns take the BF16-rounded VALU ring (the oracle's bits)."""
     ctx = bsm.Context(0)
     ctx.set_product_variant(variant)
     ctx.set_rows_per_wave(rows)
@@ -768,7 +769,7 @@ def test_mixed_product_parity(bsm, prec, b, variant, rows):
     say(f"mixed product prec={prec} b={b} variant={variant} rows={rows}")
     gp = {r: gpat(bsm, ctx, s.positions, s.box, float(r), b) for r in (6, 8, 14)}
     op = {r: O.create_pattern(s.positions, s.box, float(r)) for r in (6, 8, 14)}
-    for n, (ra, rb, rc) in enumerate([(6, 8, 14), (14, 8, 6)]):
+    for n, (ra, rb, rc) in enumerate([(6, 8, 14), (14, 8, 6), (8, 8, 14)]):
         a = synth.random_blocks(op[ra].nnz, b, 70 + n)
         bb = synth.random_blocks(op[rb].nnz, b, 80 + n)
         c0 = synth.random_blocks(op[rc].nnz, b, 90 + n)
@@ -778,7 +779,7 @@ def test_mixed_product_parity(bsm, prec, b, variant, rows):
         O.multiply_truncate_mixed(prec, 0.5, O.Matrix(op[ra], b, a), O.Matrix(op[rb], b, bb), 0.25, Co)
         err = rel_err(host(C), Co.blocks)
         say(f"   P{ra} x P{rb} -> P{rc}: {err:.3e}")
-        assert err < (2e-6 if mfma else 1e-14)
+        assert err < (2e-6 if mfma and ra == rb else 1e-14)
     ctx.close()
 
 
